@@ -1,0 +1,235 @@
+"""Seeded synthetic inputs: cell-type maps and random population states.
+
+This module holds no lattice-Boltzmann arithmetic.  It builds the workloads
+both the GPU library and the CPU oracle are run on, and nothing else; it
+imports neither of them.
+
+Cell types follow Sec. 3.3 / Fig. 5: 0 solid, 1 fluid, 2 inlet, 3 outlet.
+Inlet cells are the open cells of column 0, outlet cells the open cells of
+column nx-1.
+
+The paper's own distributor drawing (Fig. 4/5) is not available, so the
+distributor is a flat binary tree built from the description of Sec. 3.2 (an
+inlet channel that splits by successive T bifurcations into 2^L equally spaced
+outlets, channel widths shrinking per generation) at lattice resolution:
+
+  * branch centres yc(k, j) = floor((2j+1) ny / 2^(k+1)), k = 0..L, j < 2^k;
+  * junction columns xj(k) = round((k+1) nx / (L+1));
+  * the level-k bars, w_k rows wide, run from xj(k-1) (0 for k = 0) to xj(k)
+    (nx for k = L) on rows [yc - floor(w_k/2), yc - floor(w_k/2) + w_k);
+  * at xj(k) a connector w_{k+1} columns wide joins children 2j and 2j+1;
+  * rows 0 and ny-1 and every cell not in a bar or connector are solid.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SOLID, FLUID, INLET, OUTLET = 0, 1, 2, 3
+
+
+def _mark_ports(t: np.ndarray) -> np.ndarray:
+    nx = t.shape[1]
+    t[0, :] = SOLID
+    t[-1, :] = SOLID
+    col0 = t[:, 0] != SOLID
+    t[col0, 0] = INLET
+    coln = t[:, nx - 1] != SOLID
+    t[coln, nx - 1] = OUTLET
+    return t
+
+
+def default_widths(ny: int, levels: int) -> list[int]:
+    """w_0 = ny/8 halving per generation (the 1024x512 and 2048x1024
+    distributors), floored at 2."""
+    return [max(2, (ny // 8) >> k) for k in range(levels + 1)]
+
+
+def check_widths(ny: int, levels: int, widths) -> None:
+    if levels < 1 or levels > 8:
+        raise ValueError("levels must be in 1..8")
+    if len(widths) != levels + 1:
+        raise ValueError("need levels+1 widths")
+    if min(widths) < 2:
+        raise ValueError("widths must be >= 2")
+    if ny // (2 ** levels) < widths[levels] + 2:
+        raise ValueError("outlet channels do not fit: ny/2^L < w_L + 2")
+
+
+def distributor(nx: int, ny: int, levels: int, widths=None) -> np.ndarray:
+    """Flat arborescent distributor with one inlet and 2^levels outlets."""
+    widths = list(widths) if widths is not None else default_widths(ny, levels)
+    check_widths(ny, levels, widths)
+    L = levels
+    t = np.zeros((ny, nx), np.uint8)
+    xj = [int(round((k + 1) * nx / (L + 1))) for k in range(L)] + [nx]
+
+    def yc(k, j):
+        return ((2 * j + 1) * ny) // (2 ** (k + 1))
+
+    for k in range(L + 1):
+        w = widths[k]
+        xs = 0 if k == 0 else xj[k - 1]
+        xe = xj[k]
+        for j in range(2 ** k):
+            r0 = yc(k, j) - w // 2
+            t[max(r0, 0):min(r0 + w, ny), xs:xe] = FLUID
+        if k < L:
+            wc = widths[k + 1]
+            c0 = xj[k] - wc // 2
+            for j in range(2 ** k):
+                ya = yc(k + 1, 2 * j) - wc // 2
+                yb = yc(k + 1, 2 * j + 1) - wc // 2 + wc
+                t[max(ya, 0):min(yb, ny), max(c0, 0):min(c0 + wc, nx)] = FLUID
+    return _mark_ports(t)
+
+
+def channel(nx: int, ny: int) -> np.ndarray:
+    """Straight channel: solid rows 0 and ny-1, inlet column 0, outlet column
+    nx-1, fluid elsewhere (the all-fluid throughput workload and the
+    Poiseuille case)."""
+    t = np.full((ny, nx), FLUID, np.uint8)
+    return _mark_ports(t)
+
+
+def closed_box(nx: int, ny: int, obstacles: int = 0, seed: int = 0) -> np.ndarray:
+    """Fluid box with a solid frame and optional random solid cells; no
+    inlets or outlets."""
+    t = np.full((ny, nx), FLUID, np.uint8)
+    t[0, :] = t[-1, :] = SOLID
+    t[:, 0] = t[:, -1] = SOLID
+    if obstacles:
+        rng = np.random.default_rng(seed)
+        ys = rng.integers(1, ny - 1, obstacles)
+        xs = rng.integers(1, nx - 1, obstacles)
+        t[ys, xs] = SOLID
+    return t
+
+
+def random_state(types: np.ndarray, seed: int, weights, amp: float = 1e-2) -> np.ndarray:
+    """Random positive populations (9, ny, nx): weights[i] (1 + amp U(-1, 1))
+    on non-solid cells, zero on solid cells.  The caller passes the weights;
+    this module holds no lattice constant of its own."""
+    rng = np.random.default_rng(seed)
+    ny, nx = types.shape
+    w = np.asarray(weights, np.float64).reshape(9, 1, 1)
+    f = w * (1.0 + amp * rng.uniform(-1.0, 1.0, (9, ny, nx)))
+    f[:, types == SOLID] = 0.0
+    return f
+
+
+def random_field(types: np.ndarray, seed: int, umax: float = 0.05):
+    """Random (rho, ux, uy) on non-solid cells, zeros on solid cells."""
+    rng = np.random.default_rng(seed)
+    ny, nx = types.shape
+    rho = 1.0 + 1e-3 * rng.uniform(-1, 1, (ny, nx))
+    ux = umax * rng.uniform(-1, 1, (ny, nx))
+    uy = umax * rng.uniform(-1, 1, (ny, nx))
+    s = types == SOLID
+    rho[s] = 0.0
+    ux[s] = 0.0
+    uy[s] = 0.0
+    return rho, ux, uy
+
+
+def width_law_ratio(h: float, w_next: float, tol: float = 1e-12) -> float:
+    """Solve the channel-width scaling law of Sec. 3.2 (Eq. 8) for w_k given
+    w_{k+1} and channel depth h, by bisection:
+        (w_{k+1}/w_k)^4 (h + w_k)(3h + w_k) / ((h + w_{k+1})(3h + w_{k+1})) = 1/4.
+    """
+    def g(wk):
+        return (w_next / wk) ** 4 * (h + wk) * (3 * h + wk) / ((h + w_next) * (3 * h + w_next)) - 0.25
+
+    lo, hi = w_next, w_next * 4.0
+    while g(hi) > 0:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if g(mid) > 0:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo < tol * hi:
+            break
+    return 0.5 * (lo + hi)
+
+
+def width_law_chain(h: float, w_last: float, levels: int) -> list[float]:
+    """Widths w_0..w_L from the finest w_L upwards by Eq. 8."""
+    ws = [w_last]
+    for _ in range(levels):
+        ws.append(width_law_ratio(h, ws[-1]))
+    return ws[::-1]
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    levels: int
+    widths: list
+    tau: float
+    u_peak: float
+    rho_out: float = 1.0
+    seed: int = 0
+    kind: str = "distributor"
+    extra: dict = field(default_factory=dict)
+
+    def types(self) -> np.ndarray:
+        if self.kind == "channel":
+            return channel(self.nx, self.ny)
+        return distributor(self.nx, self.ny, self.levels, self.widths)
+
+
+# The five workloads the method is exercised on (names describe them).
+CORRECTNESS_128x64 = Workload("distributor-128x64-L2", 128, 64, 2, [8, 6, 4], 0.8, 0.05, seed=1,
+                              extra={"warm_steps": 5000, "iters": 10, "steps_per_iter": 5000,
+                                     "frac": 0.01})
+HEADLINE_1024x512 = Workload("distributor-1024x512-L3", 1024, 512, 3, [64, 32, 16, 8], 0.6, 0.04,
+                             seed=2, extra={"tol": 1e-6, "check_every": 100, "cap0": 500000,
+                                            "iters": 50, "cap_iter": 200000, "frac": 0.01})
+CHANNEL_1024x512 = Workload("channel-1024x512", 1024, 512, 0, [], 0.6, 0.04, seed=2, kind="channel")
+PRECISION_2048x1024 = Workload("distributor-2048x1024-L4", 2048, 1024, 4, [128, 64, 32, 16, 8],
+                               0.55, 0.03, seed=3, extra={"steps": 20000})
+CHANNEL_4096x2048 = Workload("channel-4096x2048", 4096, 2048, 0, [], 0.6, 0.04, seed=2,
+                             kind="channel")
+
+
+def batch_candidates(count: int = 256, seed: int = 4):
+    """Uneven distributor candidates: nx on {128..1024} step 64, ny on
+    {64..512} step 64, L in {2,3,4} (redrawn when the widths do not fit),
+    w_k = max(2, round(ny/8 2^-k U(0.75, 1.25))), tau ~ U[0.55, 1.0],
+    u_peak ~ U[0.02, 0.06]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        nx = int(rng.integers(2, 17)) * 64
+        ny = int(rng.integers(1, 9)) * 64
+        L = int(rng.integers(2, 5))
+        ws = [max(2, int(round(ny / 8 * 2.0 ** (-k) * rng.uniform(0.75, 1.25))))
+              for k in range(L + 1)]
+        tau = float(rng.uniform(0.55, 1.0))
+        up = float(rng.uniform(0.02, 0.06))
+        try:
+            check_widths(ny, L, ws)
+        except ValueError:
+            continue
+        out.append(Workload(f"cand{len(out)}", nx, ny, L, ws, tau, up, seed=seed))
+    return out
+
+
+def reynolds_inlet(width: float, u_in: float, nu: float) -> float:
+    """Re_in = W_in u_in / nu (Sec. 3.3)."""
+    return width * u_in / nu
+
+
+def lattice_cells(types: np.ndarray) -> tuple[int, int]:
+    """(all cells, non-solid cells)."""
+    return int(types.size), int(np.count_nonzero(types != SOLID))
+
+
+def log2i(n: int) -> int:
+    return int(math.log2(n))
