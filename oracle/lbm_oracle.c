@@ -101,12 +101,13 @@ static void moments9(const double *f, double *rho, double *jx, double *jy) {
     *jy = my;
 }
 
-/* BGK relaxation of Eq. 1 for one cell: f* = f - (f - feq)/tau. */
+/* BGK relaxation of Eq. 1 for one cell: f* = f - (1/tau)(f - feq). */
 void orc_collide_cell(const double *f, double tau, double *fout) {
     double rho, jx, jy, feq[Q];
+    const double omega = 1.0 / tau;
     moments9(f, &rho, &jx, &jy);
     orc_equilibrium(rho, jx / rho, jy / rho, feq);
-    for (int i = 0; i < Q; ++i) fout[i] = f[i] - (f[i] - feq[i]) / tau;
+    for (int i = 0; i < Q; ++i) fout[i] = f[i] - omega * (f[i] - feq[i]);
 }
 
 /* tau = 3 nu + dt/2 with dt = 1 (Sec. 2.1). */
@@ -235,11 +236,12 @@ static void moments_pass(int nx, int ny, const uint8_t *type, const double *f,
     }
 }
 
-/* Pass 4: BGK relaxation (Eq. 1) into fs. */
+/* Pass 4: BGK relaxation (Eq. 1), f* = f - (1/tau)(f - feq), into fs. */
 static void collide_pass(int nx, int ny, const uint8_t *type, const double *f,
                          const double *rho, const double *ux, const double *uy,
                          double tau, double *fs) {
     const size_t N = (size_t)nx * ny;
+    const double omega = 1.0 / tau;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
@@ -252,7 +254,7 @@ static void collide_pass(int nx, int ny, const uint8_t *type, const double *f,
             orc_equilibrium(rho[n], ux[n], uy[n], feq);
             for (int i = 0; i < Q; ++i) {
                 double fi = f[i * N + n];
-                fs[i * N + n] = fi - (fi - feq[i]) / tau;
+                fs[i * N + n] = fi - omega * (fi - feq[i]);
             }
         }
     }
