@@ -115,7 +115,9 @@ double orc_tau_from_nu(double nu) { return 3.0 * nu + 0.5; }
 
 /* Parabolic inlet profile (Sec. 3.3) on every maximal run of inlet cells in
  * column 0: rows y0..y1, walls half a cell outside the run,
- * u(y) = 4 u_peak (y - y0 + 1/2)(y1 + 1/2 - y) / W^2, W = y1 - y0 + 1.
+ * u(y) = 4 u_peak [(y - y0 + 1/2)(y1 + 1/2 - y)] / W^2, W = y1 - y0 + 1.
+ * The product of the two wall distances is formed first, so rows mirrored
+ * about the centre of the opening get bitwise equal values.
  * Rows that are not inlet cells get 0. */
 void orc_inlet_profile(int nx, int ny, const uint8_t *type, double u_peak,
                        double *uin) {
@@ -133,7 +135,7 @@ void orc_inlet_profile(int nx, int ny, const uint8_t *type, double u_peak,
         for (int r = y0; r <= y1; ++r) {
             double a = (double)(r - y0) + 0.5;
             double b = (double)(y1 - r) + 0.5;
-            uin[r] = 4.0 * u_peak * a * b / (W * W);
+            uin[r] = 4.0 * u_peak * (a * b) / (W * W);
         }
     }
 }
