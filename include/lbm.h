@@ -1,0 +1,236 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) lattice-Boltzmann shape-optimisation
+ * library.
+ *
+ * The library implements the hot path of the method of Wang, Fan & Luo,
+ * "Lattice Boltzmann method for shape optimization of fluid distributor":
+ * a D2Q9 BGK lattice-Boltzmann solve over a solid/fluid cell map (Sec. 2.1),
+ * the outlet flow-rate and pressure-drop reductions used to judge a shape
+ * (Eq. 4, Eqs. 9-11), and the constant-volume exchange of interface cells
+ * driven by the viscous-stress and dynamic-pressure criteria (Sec. 2.2,
+ * Eqs. 5-6).  The calls follow the optimisation loop of Sec. 2.3:
+ *   step (1)  lbm_create_geometry
+ *   step (2)  lbm_run_to_steady
+ *   step (3)  lbm_shape_update
+ *   step (4)  lbm_shape_update (re-initialisation) + lbm_run_to_steady
+ *   step (5)  lbm_outlet_stats (pressure drop, flow uniformity)
+ *
+ * Conventions shared by every call
+ *   - Every call returns an int status: LBM_OK (0), a warning (> 0) or an
+ *     error (< 0).  lbm_last_error() then returns a message for the calling
+ *     thread.  No C++ exception crosses this interface.
+ *   - Lattice nx x ny; cell (x, y) has the logical index n = y*nx + x
+ *     (row-major, y outer).  x = 0 is the inlet side, x = nx-1 the outlet side.
+ *   - Host arrays are owned by the caller and are only read or written during
+ *     the call; calls that fill host arrays return after the copy completed.
+ *   - A handle owns its device memory.  It is not thread-safe; distinct
+ *     handles are independent.  All device work of a handle is issued on the
+ *     stream given at creation (NULL: the null stream of the current device).
+ *   - Population index i follows the D2Q9 numbering of Sec. 2.1:
+ *     c0 = (0,0); c1..c4 = (1,0), (0,1), (-1,0), (0,-1);
+ *     c5..c8 = (1,1), (-1,1), (-1,-1), (1,-1).
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LBM_OK 0
+#define LBM_NOT_CONVERGED 1 /* run ended at max_steps above tol            */
+#define LBM_EINVAL (-1)     /* bad argument or cell map                    */
+#define LBM_ENOMEM (-2)     /* device allocation failed                    */
+#define LBM_EHIP (-3)       /* HIP runtime error                           */
+#define LBM_EUNSTABLE (-4)  /* non-finite density or velocity detected     */
+
+/* ---- cell types (Sec. 3.3, Fig. 5) ---------------------------------------
+ * Inlet cells may only sit in column 0 and outlet cells in column nx-1. */
+#define LBM_SOLID 0
+#define LBM_FLUID 1
+#define LBM_INLET 2
+#define LBM_OUTLET 3
+
+/* ---- precision forms ------------------------------------------------------
+ * LBM_F64: populations stored and relaxed in double precision.
+ * LBM_F32: populations stored as float offsets f_i - w_i, relaxed in float.
+ * Reductions (mass, fluxes, pressure drop, residual) are double in both. */
+#define LBM_F64 0
+#define LBM_F32 1
+
+/* ---- exchange-step options --------------------------------------------- */
+#define LBM_WARM 0        /* new fluid cells start at rest, rest is kept    */
+#define LBM_COLD 1        /* every non-solid cell restarts at rest          */
+#define LBM_CRIT_PAPER 0  /* Eq. 6 for fluid, Eq. 5 (summed faces) for solid */
+#define LBM_CRIT_SPEED 1  /* |u|^2 for fluid, max neighbour |u|^2 for solid */
+
+typedef struct lbm_handle lbm_handle;
+
+/* Geometry and physics of one lattice. */
+typedef struct {
+    int32_t nx, ny;     /* lattice size: 3 <= nx, 3 <= ny, nx*ny < 2^31   */
+    int32_t levels;     /* generator only: bifurcation generations L >= 1 */
+    int32_t widths[9];  /* generator only: w_0..w_L in cells; all 0 gives
+                           w_k = max(2, (ny/8) >> k)                      */
+    double tau;         /* BGK relaxation time, > 1/2 (tau = 3 nu + 1/2)  */
+    double u_peak;      /* peak of the parabolic inlet profile (lattice u)*/
+    double rho_out;     /* density imposed on outlet cells, > 0           */
+    int32_t precision;  /* LBM_F64 or LBM_F32                             */
+    int32_t reserved;   /* must be 0                                      */
+} lbm_geometry_desc;
+
+/* Boundary reductions of one state (Eq. 4, Eqs. 9-11). */
+typedef struct {
+    int32_t n_outlets;  /* maximal runs of outlet cells in column nx-1    */
+    int32_t reserved;
+    int64_t n_fluid;    /* cells of type LBM_FLUID                        */
+    int64_t n_nonsolid; /* fluid + inlet + outlet cells                   */
+    double flow_in;     /* sum of rho u_x over the inlet cells            */
+    double dp;          /* c_s^2 (mean inlet rho - mean outlet rho)        */
+    double theta;       /* max/min outlet flow, Eq. 9                      */
+    double dg;          /* maldistribution factor, Eq. 10                  */
+    double flow_ave;    /* mean outlet flow, Eq. 11                        */
+    double mass;        /* sum of rho over non-solid cells                 */
+    double residual;    /* residual of the last lbm_run_to_steady          */
+    int64_t steps;      /* time steps run since creation or set_state      */
+} lbm_stats;
+
+/* Parameters of one exchange step (Sec. 2.2, Sec. 2.3 step 3). */
+typedef struct {
+    double frac;        /* K = max(1, floor(frac * N_fluid)), 0 <= frac <= 1 */
+    uint64_t seed;      /* tie-break hash seed                               */
+    int32_t band_x;     /* cells with x < band_x or x > nx-1-band_x never flip (>= 1) */
+    int32_t band_y;     /* same for y (>= 1)                                 */
+    int32_t criterion;  /* LBM_CRIT_PAPER or LBM_CRIT_SPEED                  */
+    int32_t reinit;     /* LBM_WARM or LBM_COLD                              */
+} lbm_shape_params;
+
+/* Outcome of one exchange step. */
+typedef struct {
+    int32_t k_eff;            /* cells exchanged each way                 */
+    int32_t reserved;
+    int64_t n_cand_fluid;     /* |C_f|: fluid interface cells in the band */
+    int64_t n_cand_solid;     /* |C_s|: solid interface cells in the band */
+    int64_t n_fluid_before;
+    int64_t n_fluid_after;    /* equals n_fluid_before (constant volume)  */
+    double mass_removed;      /* sum of rho over the cells made solid     */
+    double mass_added;        /* k_eff (new fluid cells start at rho = 1) */
+} lbm_shape_result;
+
+/*
+ * Step (1) of Sec. 2.3: build a lattice and put it at rest (Sec. 3.3: the
+ * equilibrium at rho = 1, u = 0 on every non-solid cell).
+ *   d           geometry and physics; read during the call only.
+ *   cell_types  nx*ny bytes, row-major, values LBM_SOLID..LBM_OUTLET; NULL
+ *               builds the flat arborescent distributor from d->levels and
+ *               d->widths (one inlet on column 0, 2^L equally spaced outlets
+ *               on column nx-1; rows 0 and ny-1 solid).
+ *   hip_stream  hipStream_t to issue all work on, borrowed (NULL: null stream).
+ *   out         receives the handle; release it with lbm_destroy.
+ * Errors: LBM_EINVAL (sizes, tau <= 1/2, rho_out <= 0, unknown precision,
+ * ports off their column, bad generator widths), LBM_ENOMEM, LBM_EHIP.
+ */
+int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
+                        void *hip_stream, lbm_handle **out);
+
+/*
+ * Steps (2) and (4) of Sec. 2.3: advance the lattice by the LBM of Sec. 2.1
+ * (Eq. 1, Eq. 2, halfway bounce-back walls, Zou-He velocity inlet with the
+ * parabolic profile of Sec. 3.3 and Zou-He density outlets) until steady.
+ *   max_steps    at most this many time steps (>= 0).
+ *   tol          stop once r < tol; tol <= 0 runs exactly max_steps.
+ *   check_every  r = ||u(t) - u(t-k)||_2 / ||u(t)||_2 over non-solid cells,
+ *                evaluated every k = check_every steps (>= 1; the last chunk
+ *                may be shorter); u at the start of the call is the velocity
+ *                of the current state.
+ *   steps_done, residual  may be NULL.
+ * Returns LBM_OK, LBM_NOT_CONVERGED (tol > 0 not reached), LBM_EUNSTABLE
+ * (a non-finite rho or u at a check step; the state is then undefined),
+ * LBM_EINVAL, LBM_EHIP.
+ */
+int lbm_run_to_steady(lbm_handle *h, int64_t max_steps, double tol,
+                      int32_t check_every, int64_t *steps_done,
+                      double *residual);
+
+/*
+ * Step (5) of Sec. 2.3 and Sec. 4.2: boundary reductions of the current
+ * state.  flow receives the mass flux sum(rho u_x) of each outlet, ordered by
+ * increasing y (flow_cap doubles available).  All sums are double precision
+ * and run in a fixed order, so repeated calls give identical bits.
+ * Errors: LBM_EINVAL if flow_cap < n_outlets (s->n_outlets is still set), or a
+ * NULL pointer; LBM_EHIP.
+ */
+int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
+                     lbm_stats *s);
+
+/*
+ * Steps (3) and (4) of Sec. 2.3: exchange the K_eff fluid interface cells of
+ * lowest key with the K_eff solid interface cells of highest key (Sec. 2.2),
+ * at constant fluid volume, then re-initialise (WARM: new fluid cells at
+ * rest; COLD: the whole lattice at rest) and rebuild the wall links.
+ *   rho_ux_uy  NULL: keys from the current state.  Otherwise 3*nx*ny host
+ *              doubles (rho, then u_x, then u_y, each row-major) used as the
+ *              field instead.
+ * Interface: 4-neighbourhood.  Keys (criterion PAPER): fluid rho*(ux*ux +
+ * uy*uy) (Eq. 6 without the factor 1/2), solid: sum over the non-solid
+ * neighbours in the order +x, +y, -x, -y of |u_y| (x faces) or |u_x|
+ * (y faces) (Eq. 5 without mu/(0.5 dx)); both evaluated in double precision
+ * without fused multiply-add.  Ties: ascending SplitMix64(seed + n), then n.
+ * Errors: LBM_EINVAL (bad params, NaN or negative key), LBM_ENOMEM, LBM_EHIP.
+ */
+int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
+                     const double *rho_ux_uy, lbm_shape_result *r);
+
+/* Logical indices of the cells the last lbm_shape_update made solid
+ * (removed) and fluid (added), in selection order.  Returns the count k_eff
+ * (>= 0) or LBM_EINVAL when cap < k_eff. */
+int lbm_last_exchange(lbm_handle *h, int64_t *removed, int64_t *added,
+                      int32_t cap);
+
+/* Cell map, nx*ny bytes (n >= nx*ny). */
+int lbm_get_mask(lbm_handle *h, uint8_t *types, size_t n);
+
+/* Density and velocity of every cell (0 on solid cells), each nx*ny doubles
+ * (n >= nx*ny), from the current state. */
+int lbm_get_macro(lbm_handle *h, double *rho, double *ux, double *uy,
+                  size_t n);
+
+/* Current state: the post-collision populations about to stream,
+ * f[i*nx*ny + y*nx + x] for i = 0..8 (n >= 9*nx*ny doubles); solid cells 0.
+ * lbm_set_state loads such an array (solid-cell entries ignored) and resets
+ * the step counter; values are rounded to the handle's precision. */
+int lbm_get_state(lbm_handle *h, double *f, size_t n);
+int lbm_set_state(lbm_handle *h, const double *f, size_t n);
+
+/* Device bytes a handle for d would allocate (0 if d is invalid). */
+size_t lbm_footprint_bytes(const lbm_geometry_desc *d);
+
+/* Release a handle and its device memory (NULL is ignored). */
+void lbm_destroy(lbm_handle *h);
+
+/* Message of the last error on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* Advance the lattice by `steps` time steps without residual checks and
+ * report the mean time per step in milliseconds, measured with HIP events
+ * recorded on the handle's stream before the first and after the last
+ * sweep launch.  The steps are real: the state advances. */
+int lbm_bench_sweep(lbm_handle *h, int32_t steps, double *ms_per_step);
+
+/* Sweep timing inside lbm_run_to_steady.  enable = 1 resets the counters
+ * and starts recording: each residual-check interval then records a HIP
+ * event on the handle's stream before its first sweep launch and after its
+ * last plain (non-check) sweep launch, and adds the elapsed time and the
+ * number of plain sweeps in between.  enable = 0 stops recording.  Either
+ * way the current totals are returned (launches, total_ms may be NULL). */
+int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *launches,
+                       double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

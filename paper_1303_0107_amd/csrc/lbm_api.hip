@@ -1,0 +1,948 @@
+// Host implementation of the C ABI declared in include/lbm.h.
+//
+// A handle owns the device state of one lattice: two population buffers
+// (ping-pong), the cell words, the logical type map and small reduction
+// buffers.  Every call validates its arguments, issues its device work on the
+// handle's stream and returns a status; no exception crosses the interface.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const std::string &msg) {
+    g_error = msg;
+    return code;
+}
+
+struct HipFail {
+    hipError_t e;
+    const char *what;
+};
+
+#define HIP_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) throw HipFail{e_, #expr};       \
+    } while (0)
+
+struct DeviceBuffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Grow to at least `n` bytes (contents are not preserved).
+    void ensure(size_t n) {
+        if (bytes >= n) return;
+        reset();
+        if (n == 0) return;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw std::bad_alloc();
+        }
+        bytes = n;
+    }
+    template <typename U>
+    U *as() const {
+        return static_cast<U *>(p);
+    }
+    ~DeviceBuffer() { reset(); }
+};
+
+int pitch_for(int nx) { return (nx + 63) / 64 * 64; }
+
+size_t elem_size(int precision) {
+    return precision == LBM_F64 ? sizeof(double) : sizeof(float);
+}
+
+// Flat arborescent distributor: the same construction as the input
+// generator used by the tests (branch centres floor((2j+1) ny / 2^(k+1)),
+// junction columns round((k+1) nx / (L+1)) with ties to even, level-k bars
+// w_k rows wide, connectors w_{k+1} columns wide at each junction).
+bool generate_distributor(const lbm_geometry_desc &d, std::vector<uint8_t> &t,
+                          std::string &why) {
+    const int nx = d.nx, ny = d.ny, L = d.levels;
+    if (L < 1 || L > 8) {
+        why = "levels must be in 1..8";
+        return false;
+    }
+    int w[9];
+    bool all_zero = true;
+    for (int k = 0; k <= L; ++k) all_zero &= d.widths[k] == 0;
+    for (int k = 0; k <= L; ++k)
+        w[k] = all_zero ? std::max(2, (ny / 8) >> k) : d.widths[k];
+    for (int k = 0; k <= L; ++k)
+        if (w[k] < 2) {
+            why = "generator widths must be >= 2";
+            return false;
+        }
+    if (ny / (1 << L) < w[L] + 2) {
+        why = "outlet channels do not fit: ny/2^L < w_L + 2";
+        return false;
+    }
+    t.assign((size_t)nx * ny, (uint8_t)LBM_SOLID);
+    std::vector<int> xj(L + 1);
+    for (int k = 0; k < L; ++k)
+        xj[k] = (int)std::nearbyint((double)(k + 1) * nx / (double)(L + 1));
+    xj[L] = nx;
+    auto yc = [&](int k, int j) { return ((2 * j + 1) * ny) / (1 << (k + 1)); };
+    auto fill = [&](int y0, int y1, int x0, int x1) {  // half-open ranges
+        y0 = std::max(y0, 0);
+        y1 = std::min(y1, ny);
+        x0 = std::max(x0, 0);
+        x1 = std::min(x1, nx);
+        for (int y = y0; y < y1; ++y)
+            for (int x = x0; x < x1; ++x) t[(size_t)y * nx + x] = LBM_FLUID;
+    };
+    for (int k = 0; k <= L; ++k) {
+        const int xs = k == 0 ? 0 : xj[k - 1], xe = xj[k];
+        for (int j = 0; j < (1 << k); ++j) {
+            const int r0 = yc(k, j) - w[k] / 2;
+            fill(r0, r0 + w[k], xs, xe);
+        }
+        if (k < L) {
+            const int wc = w[k + 1], c0 = xj[k] - wc / 2;
+            for (int j = 0; j < (1 << k); ++j) {
+                const int ya = yc(k + 1, 2 * j) - wc / 2;
+                const int yb = yc(k + 1, 2 * j + 1) - wc / 2 + wc;
+                fill(ya, yb, c0, c0 + wc);
+            }
+        }
+    }
+    for (int x = 0; x < nx; ++x) {
+        t[x] = LBM_SOLID;
+        t[(size_t)(ny - 1) * nx + x] = LBM_SOLID;
+    }
+    for (int y = 0; y < ny; ++y) {
+        uint8_t &a = t[(size_t)y * nx];
+        if (a != LBM_SOLID) a = LBM_INLET;
+        uint8_t &b = t[(size_t)y * nx + nx - 1];
+        if (b != LBM_SOLID) b = LBM_OUTLET;
+    }
+    return true;
+}
+
+bool check_desc(const lbm_geometry_desc *d, std::string &why) {
+    if (!d) {
+        why = "null descriptor";
+        return false;
+    }
+    if (d->nx < 3 || d->ny < 3) {
+        why = "nx and ny must be >= 3";
+        return false;
+    }
+    if ((int64_t)d->nx * d->ny >= (int64_t)1 << 31) {
+        why = "nx*ny must be < 2^31";
+        return false;
+    }
+    if (!(d->tau > 0.5) || !std::isfinite(d->tau)) {
+        why = "tau must be a finite value > 1/2";
+        return false;
+    }
+    if (!(d->rho_out > 0.0) || !std::isfinite(d->rho_out)) {
+        why = "rho_out must be a finite value > 0";
+        return false;
+    }
+    if (!std::isfinite(d->u_peak) || std::fabs(d->u_peak) >= 1.0) {
+        why = "|u_peak| must be < 1";
+        return false;
+    }
+    if (d->precision != LBM_F64 && d->precision != LBM_F32) {
+        why = "unknown precision";
+        return false;
+    }
+    if (d->reserved != 0) {
+        why = "reserved field must be 0";
+        return false;
+    }
+    return true;
+}
+
+bool check_types(int nx, int ny, const uint8_t *t, std::string &why) {
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const uint8_t v = t[(size_t)y * nx + x];
+            if (v > LBM_OUTLET) {
+                why = "cell type out of range";
+                return false;
+            }
+            if (v == LBM_INLET && x != 0) {
+                why = "inlet cell outside column 0";
+                return false;
+            }
+            if (v == LBM_OUTLET && x != nx - 1) {
+                why = "outlet cell outside column nx-1";
+                return false;
+            }
+        }
+    return true;
+}
+
+}  // namespace
+
+struct lbm_handle {
+    int nx = 0, ny = 0, pitch = 0, precision = LBM_F64, device = 0;
+    size_t plane = 0;
+    double tau = 1, u_peak = 0, rho_out = 1;
+    hipStream_t stream = nullptr;
+
+    DeviceBuffer f[2];
+    int cur = 0;  // buffer holding the current state
+    DeviceBuffer cell, types, uin, uprev, partials, red, out_rows, bnd;
+    DeviceBuffer macro;  // 3*nx*ny doubles (rho, ux, uy), on demand
+    DeviceBuffer cand, sel;
+    int64_t cand_cap = 0;
+    double *pinned = nullptr;  // small host staging for readbacks
+    size_t pinned_bytes = 0;
+
+    std::vector<uint8_t> host_types;
+    std::vector<int32_t> out_y0, out_y1;
+    int64_t n_fluid = 0, n_nonsolid = 0, steps = 0;
+    double last_residual = std::nan("");
+    std::vector<int64_t> last_removed, last_added;
+    bool profiling = false;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int64_t prof_launches = 0;
+    double prof_ms = 0.0;
+
+    size_t N() const { return (size_t)nx * ny; }
+    size_t esize() const { return elem_size(precision); }
+    ~lbm_handle() {
+        if (pinned) (void)hipHostFree(pinned);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+size_t footprint(int nx, int ny, int precision) {
+    const int pitch = pitch_for(nx);
+    const size_t plane = (size_t)ny * pitch, N = (size_t)nx * ny;
+    const size_t es = elem_size(precision);
+    size_t b = 2 * 9 * plane * es;           // populations
+    b += plane * sizeof(uint16_t);           // cell words
+    b += N;                                  // type map
+    b += (size_t)ny * es;                    // inlet profile
+    b += 2 * plane * es;                     // u_prev
+    b += (size_t)sweep_blocks(nx, ny) * 4 * sizeof(double);
+    b += 3 * N * sizeof(double);             // macro field (exchange step)
+    return b;
+}
+
+void compute_ports(lbm_handle *h) {
+    const int nx = h->nx, ny = h->ny;
+    h->out_y0.clear();
+    h->out_y1.clear();
+    int y = 0;
+    while (y < ny) {
+        if (h->host_types[(size_t)y * nx + nx - 1] != LBM_OUTLET) {
+            ++y;
+            continue;
+        }
+        const int y0 = y;
+        while (y < ny && h->host_types[(size_t)y * nx + nx - 1] == LBM_OUTLET) ++y;
+        h->out_y0.push_back(y0);
+        h->out_y1.push_back(y - 1);
+    }
+    h->n_fluid = h->n_nonsolid = 0;
+    for (uint8_t v : h->host_types) {
+        h->n_fluid += v == LBM_FLUID;
+        h->n_nonsolid += v != LBM_SOLID;
+    }
+}
+
+// Parabolic inlet profile (Sec. 3.3) on each maximal run of inlet rows,
+// walls half a cell outside the run; the product of the two wall distances
+// first, so mirrored rows get bitwise equal values.
+std::vector<double> inlet_profile(const lbm_handle *h) {
+    std::vector<double> u(h->ny, 0.0);
+    int y = 0;
+    while (y < h->ny) {
+        if (h->host_types[(size_t)y * h->nx] != LBM_INLET) {
+            ++y;
+            continue;
+        }
+        const int y0 = y;
+        while (y < h->ny && h->host_types[(size_t)y * h->nx] == LBM_INLET) ++y;
+        const int y1 = y - 1;
+        const double W = (double)(y1 - y0 + 1);
+        for (int r = y0; r <= y1; ++r) {
+            const double a = (double)(r - y0) + 0.5, b = (double)(y1 - r) + 0.5;
+            u[r] = 4.0 * h->u_peak * (a * b) / (W * W);
+        }
+    }
+    return u;
+}
+
+void ensure_pinned(lbm_handle *h, size_t bytes) {
+    if (h->pinned_bytes >= bytes) return;
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    h->pinned = nullptr;
+    h->pinned_bytes = 0;
+    void *p = nullptr;
+    HIP_TRY(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    h->pinned = static_cast<double *>(p);
+    h->pinned_bytes = bytes;
+}
+
+template <typename T>
+SweepArgs<T> sweep_args(lbm_handle *h, bool check) {
+    SweepArgs<T> a;
+    a.fin = h->f[h->cur].as<T>();
+    a.fout = h->f[1 - h->cur].as<T>();
+    a.cell = h->cell.as<uint16_t>();
+    a.uin = h->uin.as<T>();
+    a.uprev = check ? h->uprev.as<T>() : nullptr;
+    a.partials = check ? h->partials.as<double>() : nullptr;
+    a.nx = h->nx;
+    a.ny = h->ny;
+    a.pitch = h->pitch;
+    a.plane = h->plane;
+    a.omega = 1.0 / h->tau;
+    a.rho_out = h->rho_out;
+    a.one_minus_rho_out = 1.0 - h->rho_out;
+    return a;
+}
+
+template <typename T>
+MacroArgs<T> macro_args(lbm_handle *h) {
+    MacroArgs<T> a;
+    a.f = h->f[h->cur].as<T>();
+    a.cell = h->cell.as<uint16_t>();
+    a.rho = a.ux = a.uy = nullptr;
+    a.uprev = nullptr;
+    a.nx = h->nx;
+    a.ny = h->ny;
+    a.pitch = h->pitch;
+    a.plane = h->plane;
+    return a;
+}
+
+template <typename T>
+void step(lbm_handle *h, bool check) {
+    HIP_TRY(launch_sweep<T>(sweep_args<T>(h, check), check, h->stream));
+    h->cur = 1 - h->cur;
+}
+
+template <typename T>
+void uprev_from_state(lbm_handle *h) {
+    MacroArgs<T> a = macro_args<T>(h);
+    a.uprev = h->uprev.as<T>();
+    HIP_TRY(launch_macro<T>(a, h->stream));
+}
+
+template <typename T>
+void macro_to_device(lbm_handle *h) {
+    h->macro.ensure(3 * h->N() * sizeof(double));
+    MacroArgs<T> a = macro_args<T>(h);
+    double *m = h->macro.as<double>();
+    a.rho = m;
+    a.ux = m + h->N();
+    a.uy = m + 2 * h->N();
+    HIP_TRY(launch_macro<T>(a, h->stream));
+}
+
+void macro_dispatch(lbm_handle *h) {
+    if (h->precision == LBM_F64)
+        macro_to_device<double>(h);
+    else
+        macro_to_device<float>(h);
+}
+
+template <typename T>
+int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
+             int64_t *steps_done, double *residual) {
+    ensure_pinned(h, 64 * sizeof(double));
+    uprev_from_state<T>(h);
+    const int64_t nblocks = sweep_blocks(h->nx, h->ny);
+    double *red = h->red.as<double>();
+    int64_t done = 0;
+    double r = h->last_residual;
+    int status = LBM_OK;
+    bool converged = false;
+    while (done < max_steps) {
+        const int64_t chunk = std::min<int64_t>(k, max_steps - done);
+        const bool timed = h->profiling && chunk > 1;
+        if (timed) HIP_TRY(hipEventRecord(h->ev[0], h->stream));
+        for (int64_t s = 0; s + 1 < chunk; ++s) step<T>(h, false);
+        if (timed) HIP_TRY(hipEventRecord(h->ev[1], h->stream));
+        step<T>(h, true);
+        HIP_TRY(launch_finalize4(h->partials.as<double>(), nblocks, red, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->pinned, red, 4 * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        done += chunk;
+        h->steps += chunk;
+        if (timed) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+            h->prof_ms += ms;
+            h->prof_launches += chunk - 1;
+        }
+        const double num = h->pinned[0], den = h->pinned[1], bad = h->pinned[3];
+        if (bad != 0.0 || !std::isfinite(num) || !std::isfinite(den)) {
+            r = std::nan("");
+            status = fail(LBM_EUNSTABLE, "non-finite density or velocity");
+            break;
+        }
+        r = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : std::sqrt(num) / std::sqrt(den);
+        if (tol > 0.0 && r < tol) {
+            converged = true;
+            break;
+        }
+    }
+    if (status == LBM_OK && tol > 0.0 && !converged) status = LBM_NOT_CONVERGED;
+    h->last_residual = r;
+    if (steps_done) *steps_done = done;
+    if (residual) *residual = r;
+    return status;
+}
+
+template <typename T>
+void stats_impl(lbm_handle *h, std::vector<double> &bout, double &mass) {
+    const int n_out = (int)h->out_y0.size();
+    const size_t nb = (size_t)(2 * n_out + 5);
+    h->bnd.ensure((nb + 1) * sizeof(double));
+    ensure_pinned(h, (nb + 1) * sizeof(double));
+    MacroArgs<T> a = macro_args<T>(h);
+    double *bo = h->bnd.as<double>();
+    HIP_TRY(launch_boundary<T>(a, h->out_rows.as<int32_t>(),
+                               h->out_rows.as<int32_t>() + std::max(n_out, 1),
+                               n_out, bo, h->stream));
+    HIP_TRY(launch_mass<T>(a, h->partials.as<double>(), h->stream));
+    HIP_TRY(launch_finalize1(h->partials.as<double>(), sweep_blocks(h->nx, h->ny),
+                             bo + nb, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->pinned, bo, (nb + 1) * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    bout.assign(h->pinned, h->pinned + nb);
+    mass = h->pinned[nb];
+}
+
+template <typename T>
+void zero_cells(lbm_handle *h, const int32_t *cells, int count) {
+    HIP_TRY(launch_rest_cells<T>(h->f[h->cur].as<T>(), h->plane, cells, count,
+                                 h->nx, h->pitch, h->stream));
+}
+
+template <typename T>
+void reset_all(lbm_handle *h) {
+    for (int b = 0; b < 2; ++b)
+        HIP_TRY(launch_rest_all<T>(h->f[b].as<T>(), h->plane, h->stream));
+}
+
+template <typename T>
+void export_state(lbm_handle *h, double *f) {
+    h->macro.ensure(3 * h->N() * sizeof(double));
+    double *stage = h->macro.as<double>();
+    for (int i = 0; i < 9; ++i) {
+        HIP_TRY(launch_export_plane<T>(h->f[h->cur].as<T>(), h->cell.as<uint16_t>(),
+                                       stage, i, h->nx, h->ny, h->pitch, h->plane,
+                                       h->stream));
+        HIP_TRY(hipMemcpyAsync(f + (size_t)i * h->N(), stage, h->N() * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+}
+
+template <typename T>
+void import_state(lbm_handle *h, const double *f) {
+    h->macro.ensure(3 * h->N() * sizeof(double));
+    double *stage = h->macro.as<double>();
+    for (int i = 0; i < 9; ++i) {
+        HIP_TRY(hipMemcpyAsync(stage, f + (size_t)i * h->N(), h->N() * sizeof(double),
+                               hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(launch_import_plane<T>(h->f[h->cur].as<T>(), h->cell.as<uint16_t>(),
+                                       stage, i, h->nx, h->ny, h->pitch, h->plane,
+                                       h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+}
+
+int guard_hip(const HipFail &f) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "HIP error %d (%s) in %s", (int)f.e,
+                  hipGetErrorString(f.e), f.what);
+    return fail(LBM_EHIP, buf);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *lbm_last_error(void) { return g_error.c_str(); }
+
+size_t lbm_footprint_bytes(const lbm_geometry_desc *d) {
+    std::string why;
+    if (!check_desc(d, why)) return 0;
+    return footprint(d->nx, d->ny, d->precision);
+}
+
+int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
+                        void *hip_stream, lbm_handle **out) {
+    g_error.clear();
+    if (!out) return fail(LBM_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    std::string why;
+    if (!check_desc(d, why)) return fail(LBM_EINVAL, why);
+    lbm_handle *h = new (std::nothrow) lbm_handle();
+    if (!h) return fail(LBM_ENOMEM, "host allocation failed");
+    try {
+        h->nx = d->nx;
+        h->ny = d->ny;
+        h->pitch = pitch_for(d->nx);
+        h->plane = (size_t)h->ny * h->pitch;
+        h->precision = d->precision;
+        h->tau = d->tau;
+        h->u_peak = d->u_peak;
+        h->rho_out = d->rho_out;
+        h->stream = static_cast<hipStream_t>(hip_stream);
+        HIP_TRY(hipGetDevice(&h->device));
+        if (cell_types) {
+            if (!check_types(h->nx, h->ny, cell_types, why)) {
+                delete h;
+                return fail(LBM_EINVAL, why);
+            }
+            h->host_types.assign(cell_types, cell_types + h->N());
+        } else if (!generate_distributor(*d, h->host_types, why)) {
+            delete h;
+            return fail(LBM_EINVAL, why);
+        }
+        compute_ports(h);
+        const size_t es = h->esize();
+        for (int b = 0; b < 2; ++b) h->f[b].ensure(9 * h->plane * es);
+        h->cell.ensure(h->plane * sizeof(uint16_t));
+        h->types.ensure(h->N());
+        h->uin.ensure((size_t)h->ny * es);
+        h->uprev.ensure(2 * h->plane * es);
+        h->partials.ensure((size_t)sweep_blocks(h->nx, h->ny) * 4 * sizeof(double));
+        h->red.ensure(64 * sizeof(double));
+        const int n_out = (int)h->out_y0.size();
+        h->out_rows.ensure(2 * (size_t)std::max(n_out, 1) * sizeof(int32_t));
+        ensure_pinned(h, 64 * sizeof(double));
+
+        HIP_TRY(hipMemcpyAsync(h->types.p, h->host_types.data(), h->N(),
+                               hipMemcpyHostToDevice, h->stream));
+        if (n_out > 0) {
+            HIP_TRY(hipMemcpyAsync(h->out_rows.p, h->out_y0.data(), n_out * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, h->stream));
+            HIP_TRY(hipMemcpyAsync(h->out_rows.as<int32_t>() + n_out, h->out_y1.data(),
+                                   n_out * sizeof(int32_t), hipMemcpyHostToDevice,
+                                   h->stream));
+        }
+        const std::vector<double> u = inlet_profile(h);
+        if (h->precision == LBM_F64) {
+            HIP_TRY(hipMemcpyAsync(h->uin.p, u.data(), h->ny * sizeof(double),
+                                   hipMemcpyHostToDevice, h->stream));
+            reset_all<double>(h);
+        } else {
+            std::vector<float> uf(u.begin(), u.end());
+            HIP_TRY(hipMemcpyAsync(h->uin.p, uf.data(), h->ny * sizeof(float),
+                                   hipMemcpyHostToDevice, h->stream));
+            reset_all<float>(h);
+        }
+        HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
+                                   h->ny, h->pitch, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    } catch (const std::bad_alloc &) {
+        delete h;
+        return fail(LBM_ENOMEM, "device allocation failed");
+    } catch (const HipFail &e) {
+        delete h;
+        return guard_hip(e);
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_handle *h) {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+int lbm_run_to_steady(lbm_handle *h, int64_t max_steps, double tol,
+                      int32_t check_every, int64_t *steps_done,
+                      double *residual) {
+    g_error.clear();
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    if (max_steps < 0 || check_every < 1 || std::isnan(tol))
+        return fail(LBM_EINVAL, "max_steps >= 0 and check_every >= 1 required");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        if (h->precision == LBM_F64)
+            return run_impl<double>(h, max_steps, tol, check_every, steps_done, residual);
+        return run_impl<float>(h, max_steps, tol, check_every, steps_done, residual);
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+}
+
+int lbm_bench_sweep(lbm_handle *h, int32_t steps, double *ms_per_step) {
+    g_error.clear();
+    if (!h || steps < 1 || !ms_per_step) return fail(LBM_EINVAL, "bad arguments");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, h->stream));
+        for (int s = 0; s < steps; ++s) {
+            if (h->precision == LBM_F64)
+                step<double>(h, false);
+            else
+                step<float>(h, false);
+        }
+        HIP_TRY(hipEventRecord(e1, h->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *ms_per_step = (double)ms / steps;
+        h->steps += steps;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return LBM_OK;
+    } catch (const HipFail &e) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return guard_hip(e);
+    }
+}
+
+int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *launches,
+                       double *total_ms) {
+    g_error.clear();
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        if (enable) {
+            for (hipEvent_t &e : h->ev)
+                if (!e) HIP_TRY(hipEventCreate(&e));
+            h->prof_launches = 0;
+            h->prof_ms = 0.0;
+        }
+        h->profiling = enable != 0;
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    }
+    if (launches) *launches = h->prof_launches;
+    if (total_ms) *total_ms = h->prof_ms;
+    return LBM_OK;
+}
+
+int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
+                     lbm_stats *s) {
+    g_error.clear();
+    if (!h || !s) return fail(LBM_EINVAL, "null handle or stats");
+    const int n_out = (int)h->out_y0.size();
+    std::memset(s, 0, sizeof *s);
+    s->n_outlets = n_out;
+    s->n_fluid = h->n_fluid;
+    s->n_nonsolid = h->n_nonsolid;
+    s->residual = h->last_residual;
+    s->steps = h->steps;
+    if (n_out > 0 && (!flow || flow_cap < n_out))
+        return fail(LBM_EINVAL, "flow_cap smaller than the number of outlets");
+    std::vector<double> b;
+    double mass = 0.0;
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        if (h->precision == LBM_F64)
+            stats_impl<double>(h, b, mass);
+        else
+            stats_impl<float>(h, b, mass);
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    for (int k = 0; k < n_out; ++k) flow[k] = b[k];
+    const double flow_in = b[2 * n_out], rho_in_sum = b[2 * n_out + 1];
+    const double cnt_in = b[2 * n_out + 2], cnt_out = b[2 * n_out + 3];
+    const double rho_out_sum = b[2 * n_out + 4];
+    const double rin = cnt_in > 0 ? rho_in_sum / cnt_in : 0.0;
+    const double rout = cnt_out > 0 ? rho_out_sum / cnt_out : 0.0;
+    s->flow_in = flow_in;
+    s->dp = (rin - rout) / 3.0;  // Eq. 4 with c_s^2 = 1/3
+    s->mass = mass;
+    if (n_out > 0) {
+        double mx = flow[0], mn = flow[0], sum = 0.0;
+        for (int k = 0; k < n_out; ++k) {
+            mx = std::max(mx, flow[k]);
+            mn = std::min(mn, flow[k]);
+            sum += flow[k];
+        }
+        const double ave = sum / n_out;  // Eq. 11
+        double dev = 0.0;
+        for (int k = 0; k < n_out; ++k) {
+            const double e = flow[k] / ave - 1.0;
+            dev += e * e;
+        }
+        s->theta = mx / mn;                                         // Eq. 9
+        s->dg = n_out > 1 ? std::sqrt(dev / (double)(n_out - 1)) : 0.0;  // Eq. 10
+        s->flow_ave = ave;
+    }
+    return LBM_OK;
+}
+
+int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
+                     const double *rho_ux_uy, lbm_shape_result *r) {
+    g_error.clear();
+    if (!h || !p || !r) return fail(LBM_EINVAL, "null argument");
+    if (!(p->frac >= 0.0 && p->frac <= 1.0))
+        return fail(LBM_EINVAL, "frac must be in [0, 1]");
+    if (p->band_x < 1 || p->band_y < 1 || 2 * p->band_x >= h->nx ||
+        2 * p->band_y >= h->ny)
+        return fail(LBM_EINVAL, "band_x, band_y must be >= 1 and leave an interior");
+    if (p->criterion != LBM_CRIT_PAPER && p->criterion != LBM_CRIT_SPEED)
+        return fail(LBM_EINVAL, "unknown criterion");
+    if (p->reinit != LBM_WARM && p->reinit != LBM_COLD)
+        return fail(LBM_EINVAL, "unknown reinit mode");
+    std::memset(r, 0, sizeof *r);
+    const size_t N = h->N();
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        h->macro.ensure(3 * N * sizeof(double));
+        double *m = h->macro.as<double>();
+        if (rho_ux_uy) {
+            HIP_TRY(hipMemcpyAsync(m, rho_ux_uy, 3 * N * sizeof(double),
+                                   hipMemcpyHostToDevice, h->stream));
+        } else {
+            macro_dispatch(h);
+        }
+        ensure_pinned(h, 64 * sizeof(double));
+        // candidate lists: 2 x (u64 key, u64 hash, i32 idx) per entry
+        if (h->cand_cap == 0) h->cand_cap = std::max<int64_t>(4096, (int64_t)(N / 16));
+        unsigned long long *counters = h->red.as<unsigned long long>() + 32;
+        int *err = reinterpret_cast<int *>(h->red.as<unsigned long long>() + 36);
+        unsigned long long cnt[2] = {0, 0};
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            const int64_t cap = h->cand_cap;
+            h->cand.ensure((size_t)cap * 2 * (2 * sizeof(uint64_t) + sizeof(int32_t)));
+            uint64_t *kf = h->cand.as<uint64_t>();
+            uint64_t *hf = kf + cap, *ks = kf + 2 * cap, *hs = kf + 3 * cap;
+            int32_t *if_ = reinterpret_cast<int32_t *>(kf + 4 * cap), *is = if_ + cap;
+            HIP_TRY(hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), h->stream));
+            HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+            KeysArgs ka;
+            ka.types = h->types.as<uint8_t>();
+            ka.rho = m;
+            ka.ux = m + N;
+            ka.uy = m + 2 * N;
+            ka.nx = h->nx;
+            ka.ny = h->ny;
+            ka.band_x = p->band_x;
+            ka.band_y = p->band_y;
+            ka.criterion = p->criterion;
+            ka.seed = p->seed;
+            ka.cap = cap;
+            ka.count_f = counters;
+            ka.count_s = counters + 1;
+            ka.error = err;
+            ka.kf = kf;
+            ka.hf = hf;
+            ka.ks = ks;
+            ka.hs = hs;
+            ka.if_ = if_;
+            ka.is = is;
+            HIP_TRY(launch_keys(ka, h->stream));
+            HIP_TRY(hipMemcpyAsync(h->pinned, counters, 5 * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            const unsigned long long *pc = reinterpret_cast<unsigned long long *>(h->pinned);
+            cnt[0] = pc[0];
+            cnt[1] = pc[1];
+            const int e = *reinterpret_cast<const int *>(pc + 4);
+            if (e != 0) return fail(LBM_EINVAL, "NaN or negative exchange key");
+            const int64_t need = (int64_t)std::max(cnt[0], cnt[1]);
+            if (need <= cap) break;
+            h->cand_cap = need;  // grow and recompute
+            h->cand.reset();
+        }
+        const int64_t cap = h->cand_cap;
+        if ((int64_t)std::max(cnt[0], cnt[1]) > cap)
+            return fail(LBM_EHIP, "candidate count changed between passes");
+        uint64_t *kf = h->cand.as<uint64_t>();
+        uint64_t *hf = kf + cap, *ks = kf + 2 * cap, *hs = kf + 3 * cap;
+        int32_t *if_ = reinterpret_cast<int32_t *>(kf + 4 * cap), *is = if_ + cap;
+        const int64_t nf = h->n_fluid;
+        int64_t K = (int64_t)std::floor(p->frac * (double)nf);
+        if (K < 1) K = 1;
+        const int64_t keff = std::min<int64_t>(K, std::min<int64_t>(cnt[0], cnt[1]));
+        r->n_cand_fluid = (int64_t)cnt[0];
+        r->n_cand_solid = (int64_t)cnt[1];
+        r->n_fluid_before = nf;
+        std::vector<int32_t> rem(keff), add(keff);
+        double mass_removed = 0.0;
+        if (keff > 0) {
+            h->sel.ensure(2 * (size_t)keff * sizeof(int32_t));
+            int32_t *srem = h->sel.as<int32_t>(), *sadd = srem + keff;
+            HIP_TRY(launch_rank(kf, hf, if_, (int64_t)cnt[0], keff, srem, h->stream));
+            HIP_TRY(launch_rank(ks, hs, is, (int64_t)cnt[1], keff, sadd, h->stream));
+            double *mass_out = h->red.as<double>() + 40;
+            HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, mass_out, m,
+                                h->stream));
+            if (p->reinit == LBM_WARM) {
+                if (h->precision == LBM_F64) {
+                    zero_cells<double>(h, srem, (int)keff);
+                    zero_cells<double>(h, sadd, (int)keff);
+                } else {
+                    zero_cells<float>(h, srem, (int)keff);
+                    zero_cells<float>(h, sadd, (int)keff);
+                }
+            }
+            HIP_TRY(hipMemcpyAsync(rem.data(), srem, keff * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipMemcpyAsync(add.data(), sadd, keff * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipMemcpyAsync(h->pinned, mass_out, sizeof(double),
+                                   hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            mass_removed = h->pinned[0];
+        }
+        if (p->reinit == LBM_COLD) {
+            if (h->precision == LBM_F64)
+                reset_all<double>(h);
+            else
+                reset_all<float>(h);
+        }
+        HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
+                                   h->ny, h->pitch, h->stream));
+        unsigned long long *fc = h->red.as<unsigned long long>() + 48;
+        HIP_TRY(hipMemsetAsync(fc, 0, sizeof(unsigned long long), h->stream));
+        HIP_TRY(launch_count_type(h->types.as<uint8_t>(), N, (uint8_t)LBM_FLUID, fc,
+                                  h->stream));
+        HIP_TRY(hipMemcpyAsync(h->pinned, fc, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const int64_t nf_after =
+            (int64_t) * reinterpret_cast<unsigned long long *>(h->pinned);
+        for (int64_t k = 0; k < keff; ++k) {
+            h->host_types[rem[k]] = LBM_SOLID;
+            h->host_types[add[k]] = LBM_FLUID;
+        }
+        h->last_removed.assign(rem.begin(), rem.end());
+        h->last_added.assign(add.begin(), add.end());
+        r->k_eff = (int32_t)keff;
+        r->n_fluid_after = nf_after;
+        r->mass_removed = mass_removed;
+        r->mass_added = (double)keff;
+        if (nf_after != nf)
+            return fail(LBM_EHIP, "fluid volume changed by the exchange step");
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "device allocation failed");
+    }
+    return LBM_OK;
+}
+
+int lbm_last_exchange(lbm_handle *h, int64_t *removed, int64_t *added,
+                      int32_t cap) {
+    g_error.clear();
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    const size_t k = h->last_removed.size();
+    if ((size_t)std::max(cap, 0) < k || (k > 0 && (!removed || !added)))
+        return fail(LBM_EINVAL, "cap smaller than the last exchange count");
+    for (size_t i = 0; i < k; ++i) {
+        removed[i] = h->last_removed[i];
+        added[i] = h->last_added[i];
+    }
+    return (int)k;
+}
+
+int lbm_get_mask(lbm_handle *h, uint8_t *types, size_t n) {
+    g_error.clear();
+    if (!h || !types || n < h->N()) return fail(LBM_EINVAL, "bad arguments");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        HIP_TRY(hipMemcpyAsync(types, h->types.p, h->N(), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    }
+    return LBM_OK;
+}
+
+int lbm_get_macro(lbm_handle *h, double *rho, double *ux, double *uy, size_t n) {
+    g_error.clear();
+    if (!h || !rho || !ux || !uy || n < h->N()) return fail(LBM_EINVAL, "bad arguments");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        macro_dispatch(h);
+        const double *m = h->macro.as<double>();
+        const size_t N = h->N();
+        HIP_TRY(hipMemcpyAsync(rho, m, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(ux, m + N, N * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipMemcpyAsync(uy, m + 2 * N, N * sizeof(double), hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_handle *h, double *f, size_t n) {
+    g_error.clear();
+    if (!h || !f || n < 9 * h->N()) return fail(LBM_EINVAL, "bad arguments");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        if (h->precision == LBM_F64)
+            export_state<double>(h, f);
+        else
+            export_state<float>(h, f);
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_handle *h, const double *f, size_t n) {
+    g_error.clear();
+    if (!h || !f || n < 9 * h->N()) return fail(LBM_EINVAL, "bad arguments");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        if (h->precision == LBM_F64)
+            import_state<double>(h, f);
+        else
+            import_state<float>(h, f);
+        h->steps = 0;
+        h->last_residual = std::nan("");
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,337 @@
+// Double-precision kernels of the D2Q9 sweep, in the reference arithmetic
+// form: populations stored as full f_i (post-collision), and every
+// floating-point expression evaluated in the order the method's definition
+// writes it (moments summed in population order, equilibrium of Sec. 2.1
+// expanded as written, relaxation f - (1/tau)(f - feq) of Eq. 1, Zou-He
+// closures as printed).  This file is compiled with -ffp-contract=off, so no
+// multiply-add is fused and each operation rounds once, as IEEE-754 double
+// arithmetic on any conforming machine does: results are reproducible bit
+// for bit.  Wang, Fan & Luo, Sec. 2.1 (Eqs. 1-2), Sec. 3.3 (boundaries),
+// Sec. 4.2 (Eqs. 9-11), Eq. 4.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace lbm {
+namespace f64 {
+
+__device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+__device__ __forceinline__ double weight(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+// rho = sum f_i, j = sum c_i f_i (Eq. 2), each summed in population order.
+__device__ __forceinline__ void moments(const double (&f)[9], double &r,
+                                        double &mx, double &my) {
+    r = 0.0;
+    mx = 0.0;
+    my = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        r += f[i];
+        mx += kCx[i] * f[i];
+        my += kCy[i] * f[i];
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
+    __shared__ double red[4][NV];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[tid >> 6][k] = v[k];
+    __syncthreads();
+    if (tid == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+}
+
+template <bool CHECK>
+__global__ __launch_bounds__(256) void sweep_kernel(SweepArgs<double> a) {
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int x = blockIdx.x * 64 + lx;
+    const int y = blockIdx.y * 4 + ly;
+    const bool in = x < a.nx && y < a.ny;
+    const size_t n = (size_t)(in ? y : 0) * a.pitch + (in ? x : 0);
+    const uint32_t cw = in ? a.cell[n] : 0u;
+    const uint32_t type = cw >> 8;
+    const bool active = in && type != kSolid;
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const size_t P = a.plane;
+        double f[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const bool wall = i > 0 && ((cw >> (i - 1)) & 1u);
+            const size_t src =
+                wall ? (size_t)kOpp[i] * P + n
+                     : (size_t)i * P + n - kCx[i] - (ptrdiff_t)kCy[i] * a.pitch;
+            f[i] = a.fin[src];
+        }
+        if (type == kInlet) {
+            const double ux = a.uin[y];
+            const double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7])) / (1.0 - ux);
+            const double ru = rho * ux;
+            f[1] = f[3] + (2.0 / 3.0) * ru;
+            f[5] = f[7] - 0.5 * (f[2] - f[4]) + (1.0 / 6.0) * ru;
+            f[8] = f[6] + 0.5 * (f[2] - f[4]) + (1.0 / 6.0) * ru;
+        } else if (type == kOutlet) {
+            const double ux =
+                -1.0 + (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8])) / a.rho_out;
+            const double ru = a.rho_out * ux;
+            f[3] = f[1] - (2.0 / 3.0) * ru;
+            f[7] = f[5] + 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * ru;
+            f[6] = f[8] - 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * ru;
+        }
+        double r, mx, my;
+        moments(f, r, mx, my);
+        const double ux = mx / r, uy = my / r;
+        const double uu = ux * ux + uy * uy;
+        const double om = a.omega;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double cu = kCx[i] * ux + kCy[i] * uy;
+            const double feq =
+                weight(i) * r * (1.0 + cu * 3.0 + 0.5 * (cu * cu) * 9.0 - 0.5 * uu * 3.0);
+            a.fout[(size_t)i * a.plane + n] = f[i] - om * (f[i] - feq);
+        }
+        if (CHECK) {
+            const double px = a.uprev[n], py = a.uprev[a.plane + n];
+            const double dx = ux - px, dy = uy - py;
+            part[0] = dx * dx + dy * dy;
+            part[1] = ux * ux + uy * uy;
+            part[2] = r;
+            part[3] = (isfinite(r) && isfinite(ux) && isfinite(uy)) ? 0.0 : 1.0;
+            a.uprev[n] = ux;
+            a.uprev[a.plane + n] = uy;
+        }
+    }
+    if (CHECK) {
+        const int tid = ly * 64 + lx;
+        block_sum<4>(part, tid);
+        if (tid == 0) {
+            const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a.partials[b * 4 + k] = part[k];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void macro_kernel(MacroArgs<double> a) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t n = (size_t)y * a.pitch + x;
+    const size_t l = (size_t)y * a.nx + x;
+    double r = 0.0, ux = 0.0, uy = 0.0;
+    if ((a.cell[n] >> 8) != kSolid) {
+        double f[9], mx, my;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = a.f[(size_t)i * a.plane + n];
+        moments(f, r, mx, my);
+        ux = mx / r;
+        uy = my / r;
+    }
+    if (a.rho) {
+        a.rho[l] = r;
+        a.ux[l] = ux;
+        a.uy[l] = uy;
+    }
+    if (a.uprev) {
+        a.uprev[n] = ux;
+        a.uprev[a.plane + n] = uy;
+    }
+}
+
+__global__ __launch_bounds__(256) void mass_kernel(MacroArgs<double> a,
+                                                   double *partials) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    double v[1] = {0.0};
+    if (x < a.nx && y < a.ny) {
+        const size_t n = (size_t)y * a.pitch + x;
+        if ((a.cell[n] >> 8) != kSolid) {
+            double f[9], mx, my;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = a.f[(size_t)i * a.plane + n];
+            moments(f, v[0], mx, my);
+        }
+    }
+    const int tid = threadIdx.y * 64 + threadIdx.x;
+    block_sum<1>(v, tid);
+    if (tid == 0) partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+}
+
+// Boundary sums in increasing y: thread k < n_out sums the x momentum of
+// outlet k; thread n_out sums x momentum and density over the inlet cells
+// and density over all outlet cells (one running sum each).  out layout:
+// [flow_0..flow_{n-1}, unused n, flow_in, rho_in, count_in, count_out, rho_out]
+__global__ void boundary_kernel(MacroArgs<double> a, const int32_t *out_y0,
+                                const int32_t *out_y1, int n_out, double *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > n_out) return;
+    auto at = [&](size_t n, double &r, double &mx) {
+        double f[9], my;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = a.f[(size_t)i * a.plane + n];
+        moments(f, r, mx, my);
+    };
+    if (k < n_out) {
+        double fl = 0.0;
+        for (int y = out_y0[k]; y <= out_y1[k]; ++y) {
+            double r, mx;
+            at((size_t)y * a.pitch + (a.nx - 1), r, mx);
+            fl += mx;
+        }
+        out[k] = fl;
+        out[n_out + k] = 0.0;
+    } else {
+        double fl = 0.0, rin = 0.0, rout = 0.0, cin = 0.0, cout = 0.0;
+        for (int y = 0; y < a.ny; ++y) {
+            const size_t n0 = (size_t)y * a.pitch;
+            double r, mx;
+            if ((a.cell[n0 + a.nx - 1] >> 8) == kOutlet) {
+                at(n0 + a.nx - 1, r, mx);
+                rout += r;
+                cout += 1.0;
+            }
+            if ((a.cell[n0] >> 8) == kInlet) {
+                at(n0, r, mx);
+                fl += mx;
+                rin += r;
+                cin += 1.0;
+            }
+        }
+        out[2 * n_out + 0] = fl;
+        out[2 * n_out + 1] = rin;
+        out[2 * n_out + 2] = cin;
+        out[2 * n_out + 3] = cout;
+        out[2 * n_out + 4] = rout;
+    }
+}
+
+__global__ void rest_cells_kernel(double *f, size_t plane, const int32_t *cells,
+                                  int count, int nx, int pitch) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int l = cells[k];
+    const size_t n = (size_t)(l / nx) * pitch + (l % nx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[(size_t)i * plane + n] = weight(i);
+}
+
+__global__ void rest_all_kernel(double *f, size_t plane) {
+    for (size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x; j < plane;
+         j += (size_t)gridDim.x * blockDim.x)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[(size_t)i * plane + j] = weight(i);
+}
+
+__global__ __launch_bounds__(256) void export_plane_kernel(
+    const double *f, const uint16_t *cell, double *out, int i, int nx, int ny,
+    int pitch, size_t plane) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= nx || y >= ny) return;
+    const size_t n = (size_t)y * pitch + x;
+    out[(size_t)y * nx + x] = (cell[n] >> 8) == kSolid ? 0.0 : f[(size_t)i * plane + n];
+}
+
+__global__ __launch_bounds__(256) void import_plane_kernel(
+    double *f, const uint16_t *cell, const double *in, int i, int nx, int ny,
+    int pitch, size_t plane) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= nx || y >= ny) return;
+    const size_t n = (size_t)y * pitch + x;
+    f[(size_t)i * plane + n] = (cell[n] >> 8) == kSolid ? weight(i) : in[(size_t)y * nx + x];
+}
+
+}  // namespace f64
+
+static inline dim3 grid_cells(int ncols, int ny) {
+    return dim3((unsigned)((ncols + 63) / 64), (unsigned)((ny + 3) / 4));
+}
+
+template <>
+hipError_t launch_sweep<double>(const SweepArgs<double> &a, bool check,
+                                hipStream_t s) {
+    const dim3 g = grid_cells(a.nx, a.ny), b(64, 4);
+    if (check)
+        hipLaunchKernelGGL(f64::sweep_kernel<true>, g, b, 0, s, a);
+    else
+        hipLaunchKernelGGL(f64::sweep_kernel<false>, g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_macro<double>(const MacroArgs<double> &a, hipStream_t s) {
+    hipLaunchKernelGGL(f64::macro_kernel, grid_cells(a.nx, a.ny), dim3(64, 4), 0, s, a);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_mass<double>(const MacroArgs<double> &a, double *partials,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(f64::mass_kernel, grid_cells(a.nx, a.ny), dim3(64, 4), 0, s, a,
+                       partials);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_boundary<double>(const MacroArgs<double> &a, const int32_t *y0,
+                                   const int32_t *y1, int n_out, double *out,
+                                   hipStream_t s) {
+    const int threads = n_out + 1;
+    hipLaunchKernelGGL(f64::boundary_kernel, dim3((threads + 63) / 64), dim3(64), 0, s, a,
+                       y0, y1, n_out, out);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_rest_cells<double>(double *f, size_t plane, const int32_t *cells,
+                                     int count, int nx, int pitch, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(f64::rest_cells_kernel, dim3((count + 255) / 256), dim3(256), 0, s,
+                       f, plane, cells, count, nx, pitch);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_rest_all<double>(double *f, size_t plane, hipStream_t s) {
+    size_t blocks = (plane + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(f64::rest_all_kernel, dim3((unsigned)blocks), dim3(256), 0, s, f,
+                       plane);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_export_plane<double>(const double *f, const uint16_t *cell, double *out,
+                                       int i, int nx, int ny, int pitch, size_t plane,
+                                       hipStream_t s) {
+    hipLaunchKernelGGL(f64::export_plane_kernel, grid_cells(nx, ny), dim3(64, 4), 0, s, f,
+                       cell, out, i, nx, ny, pitch, plane);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_import_plane<double>(double *f, const uint16_t *cell, const double *in,
+                                       int i, int nx, int ny, int pitch, size_t plane,
+                                       hipStream_t s) {
+    hipLaunchKernelGGL(f64::import_plane_kernel, grid_cells(nx, ny), dim3(64, 4), 0, s, f,
+                       cell, in, i, nx, ny, pitch, plane);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

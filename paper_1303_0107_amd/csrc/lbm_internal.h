@@ -1,0 +1,125 @@
+// Internal declarations shared by the kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum : uint32_t { kSolid = 0, kFluid = 1, kInlet = 2, kOutlet = 3 };
+enum : int { kCritPaper = 0, kCritSpeed = 1 };
+
+// Arguments of one sweep launch.  Populations live in nine planes of `plane`
+// elements (ny rows of `pitch`).  Single precision stores the offsets
+// d_i = f_i - w_i; double precision stores f_i (see lbm_f64.hip).
+template <typename T>
+struct SweepArgs {
+    const T *fin;
+    T *fout;
+    const uint16_t *cell;
+    const T *uin;      // inlet velocity per row
+    T *uprev;          // two planes (u_x, u_y); check steps only
+    double *partials;  // 4 doubles per block; check steps only
+    int nx, ny, pitch;
+    size_t plane;
+    double omega;      // 1 / tau
+    double rho_out;
+    double one_minus_rho_out;
+};
+
+template <typename T>
+struct MacroArgs {
+    const T *f;
+    const uint16_t *cell;
+    double *rho, *ux, *uy;  // logical layout, optional
+    T *uprev;               // pitched, optional
+    int nx, ny, pitch;
+    size_t plane;
+};
+
+struct KeysArgs {
+    const uint8_t *types;  // logical layout
+    const double *rho, *ux, *uy;
+    int nx, ny, band_x, band_y, criterion;
+    uint64_t seed;
+    int64_t cap;
+    unsigned long long *count_f, *count_s;
+    int *error;
+    uint64_t *kf, *hf, *ks, *hs;
+    int32_t *if_, *is;
+};
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T> &a, bool check, hipStream_t s);
+int64_t sweep_blocks(int nx, int ny);
+hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
+                            hipStream_t s);
+hipError_t launch_finalize1(const double *partials, int64_t count, double *out,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_macro(const MacroArgs<T> &a, hipStream_t s);
+template <typename T>
+hipError_t launch_mass(const MacroArgs<T> &a, double *partials, hipStream_t s);
+template <typename T>
+hipError_t launch_boundary(const MacroArgs<T> &a, const int32_t *y0,
+                           const int32_t *y1, int n_out, double *out,
+                           hipStream_t s);
+hipError_t launch_build_cells(const uint8_t *types, uint16_t *cell, int nx,
+                              int ny, int pitch, hipStream_t s);
+// Put the given cells (logical indices) / the whole buffer at rest
+// (f_i = w_i: offsets 0 in single precision, w_i in double precision).
+template <typename T>
+hipError_t launch_rest_cells(T *f, size_t plane, const int32_t *cells,
+                             int count, int nx, int pitch, hipStream_t s);
+template <typename T>
+hipError_t launch_rest_all(T *f, size_t plane, hipStream_t s);
+template <typename T>
+hipError_t launch_export_plane(const T *f, const uint16_t *cell, double *out,
+                               int i, int nx, int ny, int pitch, size_t plane,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_import_plane(T *f, const uint16_t *cell, const double *in,
+                               int i, int nx, int ny, int pitch, size_t plane,
+                               hipStream_t s);
+hipError_t launch_keys(const KeysArgs &a, hipStream_t s);
+hipError_t launch_rank(const uint64_t *key, const uint64_t *hash,
+                       const int32_t *idx, int64_t count, int64_t k_eff,
+                       int32_t *sel, hipStream_t s);
+hipError_t launch_flip(uint8_t *types, const int32_t *removed,
+                       const int32_t *added, int k_eff, double *mass_out,
+                       const double *rho, hipStream_t s);
+hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
+                             unsigned long long *out, hipStream_t s);
+
+// Double-precision specialisations, defined in lbm_f64.hip.
+template <>
+hipError_t launch_sweep<double>(const SweepArgs<double> &a, bool check, hipStream_t s);
+template <>
+hipError_t launch_macro<double>(const MacroArgs<double> &a, hipStream_t s);
+template <>
+hipError_t launch_mass<double>(const MacroArgs<double> &a, double *partials, hipStream_t s);
+template <>
+hipError_t launch_boundary<double>(const MacroArgs<double> &a, const int32_t *y0,
+                                   const int32_t *y1, int n_out, double *out, hipStream_t s);
+template <>
+hipError_t launch_rest_cells<double>(double *f, size_t plane, const int32_t *cells,
+                                     int count, int nx, int pitch, hipStream_t s);
+template <>
+hipError_t launch_rest_all<double>(double *f, size_t plane, hipStream_t s);
+template <>
+hipError_t launch_export_plane<double>(const double *f, const uint16_t *cell, double *out,
+                                       int i, int nx, int ny, int pitch, size_t plane,
+                                       hipStream_t s);
+template <>
+hipError_t launch_import_plane<double>(double *f, const uint16_t *cell, const double *in,
+                                       int i, int nx, int ny, int pitch, size_t plane,
+                                       hipStream_t s);
+// Single-precision specialisations, defined in lbm_kernels.hip.
+template <>
+hipError_t launch_rest_cells<float>(float *f, size_t plane, const int32_t *cells,
+                                    int count, int nx, int pitch, hipStream_t s);
+template <>
+hipError_t launch_rest_all<float>(float *f, size_t plane, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,692 @@
+// Single-precision sweep kernels and the precision-independent kernels (cell
+// words, exchange step) of the D2Q9 lattice-Boltzmann shape-optimisation path
+// for gfx950 (MI355X).  The double-precision sweep lives in lbm_f64.hip.
+// Wang, Fan & Luo, "Lattice Boltzmann method for shape optimization of fluid
+// distributor": Sec. 2.1 (LBE, equilibrium, moments),
+// Sec. 2.2 (exchange criteria, Eqs. 5-6), Sec. 3.3 (boundary conditions),
+// Sec. 4.2 (Eqs. 9-11), Eq. 4 (pressure).
+//
+// Memory layout (see lbm_internal.h):
+//   populations  nine planes of ny rows x pitch columns, pitch a multiple of
+//                64 so that every wavefront row segment is 64 consecutive
+//                elements.  Single precision stores the offset d_i = f_i - w_i
+//                of the post-collision population (about to stream), which
+//                keeps the relative precision of the small deviations from
+//                rest; double precision stores f_i itself.
+//   cell words   uint16 per cell: bits 0..7 flag a wall on the pull link of
+//                population 1..8 (source solid or outside the lattice),
+//                bits 8..9 the cell type.
+//   two population buffers, read one / write the other each step.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_internal.h"
+
+namespace lbm {
+
+// D2Q9 numbering of Sec. 2.1.
+__device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+template <typename T>
+__device__ __forceinline__ T wgt(int i) {
+    return i == 0 ? T(4) / T(9) : (i < 5 ? T(1) / T(9) : T(1) / T(36));
+}
+
+// Moments of nine offsets with the mirror-symmetric pairing of the sweep:
+// density offset, x and y momentum.
+__device__ __forceinline__ void moments_sym(const double (&d)[9], double &dr,
+                                            double &jx, double &jy) {
+    dr = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[8]) + (d[6] + d[7]));
+    jx = (d[1] + (d[5] + d[8])) - (d[3] + (d[6] + d[7]));
+    jy = (d[2] + (d[5] + d[6])) - (d[4] + (d[8] + d[7]));
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront / block reductions of NV doubles (fixed order: results do not
+// depend on scheduling).
+template <int NV>
+__device__ __forceinline__ void wave_sum(double (&v)[NV]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_xor(v[k], off, 64);
+}
+
+// Sum over a block of `nthreads` (multiple of 64, <= 1024); the result is
+// valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], int tid,
+                                          int nthreads) {
+    __shared__ double red[16][NV];
+    wave_sum<NV>(v);
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+        const int nw = nthreads >> 6;
+        for (int w = 1; w < nw; ++w)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] += red[w][k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One time step (Eq. 1): pull streaming with halfway bounce-back, Zou-He
+// boundaries on inlet / outlet cells, moments (Eq. 2), BGK relaxation to the
+// second-order equilibrium.  With CHECK the step also accumulates, per
+// block, sum |u - u_prev|^2, sum |u|^2, sum rho and the number of non-finite
+// cells, and stores u as the new u_prev.
+#ifndef LBM_F32_COMPUTE
+#define LBM_F32_COMPUTE double
+#endif
+
+// Single-precision storage, arithmetic in CT (double by default: with float
+// storage the rounding of the arithmetic, not of the stored offsets,
+// dominates the error of steady fields).  Every sum pairs the populations
+// that a reflection y -> -y exchanges (2<->4, 5<->8, 6<->7), and every
+// product is formed so that such a reflection maps it to itself or to its
+// exact negative: on a mirror-symmetric lattice the computed flow is then
+// mirror-symmetric bit for bit, and rounding cannot feed the slow
+// antisymmetric mode (the flux split between the two halves of a tree).
+template <typename T, bool CHECK, typename CT = LBM_F32_COMPUTE>
+__global__ __launch_bounds__(256) void sweep_kernel(SweepArgs<T> a) {
+    const int lx = threadIdx.x;                  // 0..63
+    const int ly = threadIdx.y;                  // 0..3
+    const int x = blockIdx.x * 64 + lx;
+    const int y = blockIdx.y * 4 + ly;
+    const bool in = x < a.nx && y < a.ny;
+    const size_t n = (size_t)(in ? y : 0) * a.pitch + (in ? x : 0);
+    const uint32_t cw = in ? a.cell[n] : 0u;
+    const uint32_t type = cw >> 8;
+    const bool active = in && type != kSolid;
+
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const size_t P = a.plane;
+        CT d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const bool wall = i > 0 && ((cw >> (i - 1)) & 1u);
+            const size_t src =
+                wall ? (size_t)kOpp[i] * P + n
+                     : (size_t)i * P + n - kCx[i] - (ptrdiff_t)kCy[i] * a.pitch;
+            d[i] = (CT)a.fin[src];
+        }
+        if (type == kInlet) {
+            // velocity (u_in(y), 0) imposed; unknowns 1, 5, 8
+            const CT ux = (CT)a.uin[y];
+            const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[3] + (d[6] + d[7]));
+            const CT dr = (s + ux) / (CT(1) - ux);
+            const CT ru = (CT(1) + dr) * ux;
+            const CT h = CT(0.5) * (d[2] - d[4]);
+            d[1] = d[3] + (CT(2) / CT(3)) * ru;
+            d[5] = d[7] - h + (CT(1) / CT(6)) * ru;
+            d[8] = d[6] + h + (CT(1) / CT(6)) * ru;
+        } else if (type == kOutlet) {
+            // density rho_out and zero transverse velocity; unknowns 3, 6, 7
+            const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[1] + (d[5] + d[8]));
+            const CT ux = (s + (CT)a.one_minus_rho_out) / (CT)a.rho_out;
+            const CT ru = (CT)a.rho_out * ux;
+            const CT h = CT(0.5) * (d[2] - d[4]);
+            d[3] = d[1] - (CT(2) / CT(3)) * ru;
+            d[7] = d[5] + h - (CT(1) / CT(6)) * ru;
+            d[6] = d[8] - h - (CT(1) / CT(6)) * ru;
+        }
+        const CT dr = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[8]) + (d[6] + d[7]));
+        const CT rho = CT(1) + dr;
+        const CT jx = (d[1] + (d[5] + d[8])) - (d[3] + (d[6] + d[7]));
+        const CT jy = (d[2] + (d[5] + d[6])) - (d[4] + (d[8] + d[7]));
+        const CT ir = CT(1) / rho;
+        const CT ux = jx * ir, uy = jy * ir;
+        const CT uu15 = CT(1.5) * (ux * ux + uy * uy);
+        const CT om = (CT)a.omega;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const CT cu = CT(kCx[i]) * ux + CT(kCy[i]) * uy;
+            const CT deq =
+                wgt<CT>(i) * (dr + rho * (CT(3) * cu + CT(4.5) * cu * cu - uu15));
+            a.fout[(size_t)i * a.plane + n] = (T)(d[i] + om * (deq - d[i]));
+        }
+        if (CHECK) {
+            const size_t m = (size_t)y * a.pitch + x;
+            const double px = (double)a.uprev[m];
+            const double py = (double)a.uprev[a.plane + m];
+            const double dx = (double)ux - px, dy = (double)uy - py;
+            part[0] = dx * dx + dy * dy;
+            part[1] = (double)ux * (double)ux + (double)uy * (double)uy;
+            part[2] = 1.0 + (double)dr;
+            const bool fin = isfinite((double)rho) && isfinite((double)ux) &&
+                             isfinite((double)uy);
+            part[3] = fin ? 0.0 : 1.0;
+            a.uprev[m] = (T)ux;
+            a.uprev[a.plane + m] = (T)uy;
+        }
+    }
+    if (CHECK) {
+        const int tid = ly * 64 + lx;
+        block_sum<4>(part, tid, 256);
+        if (tid == 0) {
+            const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a.partials[b * 4 + k] = part[k];
+        }
+    }
+}
+
+// Sum `count` groups of NV doubles in a fixed order (one block of 256).
+template <int NV>
+__global__ __launch_bounds__(256) void finalize_kernel(const double *partials,
+                                                       int64_t count,
+                                                       double *out) {
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int64_t j = threadIdx.x; j < count; j += 256)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += partials[j * NV + k];
+    block_sum<NV>(v, threadIdx.x, 256);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) out[k] = v[k];
+}
+
+// ---------------------------------------------------------------------------
+// Moments of the stored state (collision conserves rho and rho u, so these
+// equal the moments of the state it was relaxed from).  Optional outputs:
+// double rho/ux/uy in logical layout (y*nx + x; zero on solid cells), and
+// the u_prev planes (pitched, type T).
+template <typename T>
+__global__ __launch_bounds__(256) void macro_kernel(MacroArgs<T> a) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= a.nx || y >= a.ny) return;
+    const size_t n = (size_t)y * a.pitch + x;
+    const size_t l = (size_t)y * a.nx + x;
+    const bool solid = (a.cell[n] >> 8) == kSolid;
+    double rho = 0.0, ux = 0.0, uy = 0.0;
+    if (!solid) {
+        double d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = (double)a.f[(size_t)i * a.plane + n];
+        double dr, jx, jy;
+        moments_sym(d, dr, jx, jy);
+        rho = 1.0 + dr;
+        ux = jx / rho;
+        uy = jy / rho;
+    }
+    if (a.rho) {
+        a.rho[l] = rho;
+        a.ux[l] = ux;
+        a.uy[l] = uy;
+    }
+    if (a.uprev) {
+        a.uprev[n] = (T)ux;
+        a.uprev[a.plane + n] = (T)uy;
+    }
+}
+
+// Per-block sum of rho over non-solid cells of the stored state.
+template <typename T>
+__global__ __launch_bounds__(256) void mass_kernel(MacroArgs<T> a,
+                                                   double *partials) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    double v[1] = {0.0};
+    if (x < a.nx && y < a.ny) {
+        const size_t n = (size_t)y * a.pitch + x;
+        if ((a.cell[n] >> 8) != kSolid) {
+            double d[9], dr, jx, jy;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) d[i] = (double)a.f[(size_t)i * a.plane + n];
+            moments_sym(d, dr, jx, jy);
+            v[0] = 1.0 + dr;
+        }
+    }
+    const int tid = threadIdx.y * 64 + threadIdx.x;
+    block_sum<1>(v, tid, 256);
+    if (tid == 0) partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
+}
+
+// Boundary sums (Sec. 4.2) in increasing y: thread k < n_out sums rho u_x
+// and rho over outlet k's rows y0..y1 (column nx-1); thread n_out sums over
+// the inlet cells of column 0 and the density over all outlet cells.  out:
+// [flow_0..flow_{n-1}, rho_0..rho_{n-1}, flow_in, rho_in, count_in,
+//  count_out, rho_out]
+template <typename T>
+__global__ void boundary_kernel(MacroArgs<T> a, const int32_t *out_y0,
+                                const int32_t *out_y1, int n_out,
+                                double *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > n_out) return;
+    auto moments = [&](size_t n, double &rho, double &jx) {
+        double d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = (double)a.f[(size_t)i * a.plane + n];
+        double dr, jy;
+        moments_sym(d, dr, jx, jy);
+        rho = 1.0 + dr;
+    };
+    if (k < n_out) {
+        double fl = 0.0, rs = 0.0;
+        for (int y = out_y0[k]; y <= out_y1[k]; ++y) {
+            double r, j;
+            moments((size_t)y * a.pitch + (a.nx - 1), r, j);
+            fl += j;
+            rs += r;
+        }
+        out[k] = fl;
+        out[n_out + k] = rs;
+    } else {
+        double fl = 0.0, rs = 0.0, cnt = 0.0, cnt_out = 0.0, rout = 0.0;
+        for (int y = 0; y < a.ny; ++y) {
+            const size_t n = (size_t)y * a.pitch;
+            double r, j;
+            if ((a.cell[n + a.nx - 1] >> 8) == kOutlet) {
+                moments(n + a.nx - 1, r, j);
+                rout += r;
+                cnt_out += 1.0;
+            }
+            if ((a.cell[n] >> 8) == kInlet) {
+                moments(n, r, j);
+                fl += j;
+                rs += r;
+                cnt += 1.0;
+            }
+        }
+        out[2 * n_out + 0] = fl;
+        out[2 * n_out + 1] = rs;
+        out[2 * n_out + 2] = cnt;
+        out[2 * n_out + 3] = cnt_out;
+        out[2 * n_out + 4] = rout;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cell words from the logical type map: wall bit of population i set when
+// the pull source x - c_i is solid or off the lattice.  Pad columns are solid.
+__global__ __launch_bounds__(256) void build_cells_kernel(const uint8_t *types,
+                                                          uint16_t *cell,
+                                                          int nx, int ny,
+                                                          int pitch) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= pitch || y >= ny) return;
+    uint32_t w = 0;
+    if (x < nx) {
+        const uint32_t t = types[(size_t)y * nx + x];
+        w = t << 8;
+        if (t != kSolid) {
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int sx = x - kCx[i], sy = y - kCy[i];
+                const bool wall = sx < 0 || sx >= nx || sy < 0 || sy >= ny ||
+                                  types[(size_t)sy * nx + sx] == kSolid;
+                w |= (wall ? 1u : 0u) << (i - 1);
+            }
+        }
+    }
+    cell[(size_t)y * pitch + x] = (uint16_t)w;
+}
+
+// Every population offset of the given cells to zero: the rest equilibrium
+// f_i = w_i.
+template <typename T>
+__global__ void zero_cells_kernel(T *f, size_t plane, const int32_t *cells,
+                                  int count, int nx, int pitch) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int l = cells[k];
+    const size_t n = (size_t)(l / nx) * pitch + (l % nx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[(size_t)i * plane + n] = T(0);
+}
+
+template <typename T>
+__global__ void fill_kernel(T *p, size_t count, T v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// State export / import of one population plane: f = w_i + d (0 on solid
+// cells) in logical layout.
+template <typename T>
+__global__ __launch_bounds__(256) void export_plane_kernel(
+    const T *f, const uint16_t *cell, double *out, int i, int nx, int ny,
+    int pitch, size_t plane) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= nx || y >= ny) return;
+    const size_t n = (size_t)y * pitch + x;
+    const bool solid = (cell[n] >> 8) == kSolid;
+    out[(size_t)y * nx + x] =
+        solid ? 0.0 : wgt<double>(i) + (double)f[(size_t)i * plane + n];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void import_plane_kernel(
+    T *f, const uint16_t *cell, const double *in, int i, int nx, int ny,
+    int pitch, size_t plane) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x >= nx || y >= ny) return;
+    const size_t n = (size_t)y * pitch + x;
+    const bool solid = (cell[n] >> 8) == kSolid;
+    f[(size_t)i * plane + n] =
+        solid ? T(0) : (T)(in[(size_t)y * nx + x] - wgt<double>(i));
+}
+
+// ---------------------------------------------------------------------------
+// Exchange step (Sec. 2.2).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t state) {
+    // SplitMix64 output function (Steele, Lea & Flood 2014) on state + gamma
+    uint64_t z = state + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Order-preserving integer image of a key >= 0 (-0 folded onto +0).
+__device__ __forceinline__ uint64_t key_bits(double k) {
+    return k == 0.0 ? 0ull : (uint64_t)__double_as_longlong(k);
+}
+
+// Candidate keys of the interface cells inside the band.  Fluid candidates
+// sort ascending on (key, hash, idx); solid candidates descending on key,
+// which is stored complemented so that both lists sort ascending.
+__global__ __launch_bounds__(256) void keys_kernel(KeysArgs a) {
+#pragma clang fp contract(off)
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    if (x < a.band_x || x > a.nx - 1 - a.band_x || y < a.band_y ||
+        y > a.ny - 1 - a.band_y)
+        return;
+    const int nx = a.nx;
+    const size_t l = (size_t)y * nx + x;
+    const uint8_t t = a.types[l];
+    if (t != kFluid && t != kSolid) return;
+    const int ddx[4] = {1, 0, -1, 0};
+    const int ddy[4] = {0, 1, 0, -1};
+    bool touch = false;
+    double key = 0.0;
+    bool bad = false;
+    if (t == kFluid) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            touch |= a.types[l + ddx[d] + (ptrdiff_t)ddy[d] * nx] == kSolid;
+        if (!touch) return;
+        const double ux = a.ux[l], uy = a.uy[l];
+        const double t1 = ux * ux;
+        const double t2 = uy * uy;
+        const double t3 = t1 + t2;
+        key = a.criterion == kCritPaper ? a.rho[l] * t3 : t3;
+    } else {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const size_t m = l + ddx[d] + (ptrdiff_t)ddy[d] * nx;
+            if (a.types[m] == kSolid) continue;
+            touch = true;
+            if (a.criterion == kCritPaper) {
+                const double tang = ddx[d] != 0 ? fabs(a.uy[m]) : fabs(a.ux[m]);
+                key = key + tang;
+            } else {
+                const double t1 = a.ux[m] * a.ux[m];
+                const double t2 = a.uy[m] * a.uy[m];
+                const double s = t1 + t2;
+                if (!(s >= 0.0)) bad = true;
+                if (s > key) key = s;
+            }
+        }
+        if (!touch) return;
+    }
+    if (!(key >= 0.0)) bad = true;
+    if (bad) {
+        atomicOr(a.error, 1);
+        return;
+    }
+    const uint64_t kb = key_bits(key);
+    const uint64_t h = splitmix64(a.seed + (uint64_t)l);
+    if (t == kFluid) {
+        const unsigned long long s = atomicAdd(a.count_f, 1ull);
+        if (s < (unsigned long long)a.cap) {
+            a.kf[s] = kb;
+            a.hf[s] = h;
+            a.if_[s] = (int32_t)l;
+        }
+    } else {
+        const unsigned long long s = atomicAdd(a.count_s, 1ull);
+        if (s < (unsigned long long)a.cap) {
+            a.ks[s] = ~kb;
+            a.hs[s] = h;
+            a.is[s] = (int32_t)l;
+        }
+    }
+}
+
+__device__ __forceinline__ bool comp_less(uint64_t ka, uint64_t ha, int32_t ia,
+                                          uint64_t kb, uint64_t hb,
+                                          int32_t ib) {
+    if (ka != kb) return ka < kb;
+    if (ha != hb) return ha < hb;
+    return ia < ib;
+}
+
+// Rank of every candidate in its list (number of candidates ordered before
+// it); those with rank < k_eff are written to sel[rank].  Tiles of the list
+// are staged in LDS.  Ranks are unique because the indices are.
+__global__ __launch_bounds__(256) void rank_kernel(const uint64_t *key,
+                                                   const uint64_t *hash,
+                                                   const int32_t *idx,
+                                                   int64_t count,
+                                                   int64_t k_eff,
+                                                   int32_t *sel) {
+    __shared__ uint64_t sk[256];
+    __shared__ uint64_t sh[256];
+    __shared__ int32_t si[256];
+    const int64_t me = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = me < count;
+    const uint64_t mk = valid ? key[me] : 0, mh = valid ? hash[me] : 0;
+    const int32_t mi = valid ? idx[me] : 0;
+    int64_t rank = 0;
+    for (int64_t base = 0; base < count; base += 256) {
+        const int64_t j = base + threadIdx.x;
+        if (j < count) {
+            sk[threadIdx.x] = key[j];
+            sh[threadIdx.x] = hash[j];
+            si[threadIdx.x] = idx[j];
+        }
+        __syncthreads();
+        const int lim = (int)((count - base) < 256 ? (count - base) : 256);
+        if (valid)
+            for (int t = 0; t < lim; ++t)
+                rank += comp_less(sk[t], sh[t], si[t], mk, mh, mi) ? 1 : 0;
+        __syncthreads();
+    }
+    if (valid && rank < k_eff) sel[rank] = mi;
+}
+
+// Apply the exchange to the logical type map.
+__global__ void flip_kernel(uint8_t *types, const int32_t *removed,
+                            const int32_t *added, int k_eff) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= k_eff) return;
+    types[removed[k]] = kSolid;
+    types[added[k]] = kFluid;
+}
+
+// Sum of rho over the removed cells in selection order (one thread).
+__global__ void removed_mass_kernel(const double *rho, const int32_t *removed,
+                                    int k_eff, double *out) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int k = 0; k < k_eff; ++k) s += rho[removed[k]];
+    out[0] = s;
+}
+
+__global__ __launch_bounds__(256) void count_type_kernel(const uint8_t *types,
+                                                         size_t count,
+                                                         uint8_t which,
+                                                         unsigned long long *out) {
+    unsigned long long c = 0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count;
+         i += (size_t)gridDim.x * 256)
+        c += types[i] == which;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+static inline dim3 grid_cells(int ncols, int ny) {
+    return dim3((unsigned)((ncols + 63) / 64), (unsigned)((ny + 3) / 4));
+}
+
+template <typename T>
+hipError_t launch_sweep(const SweepArgs<T> &a, bool check, hipStream_t s) {
+    const dim3 g = grid_cells(a.nx, a.ny), b(64, 4);
+    if (check)
+        hipLaunchKernelGGL((sweep_kernel<T, true>), g, b, 0, s, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<T, false>), g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+int64_t sweep_blocks(int nx, int ny) {
+    const dim3 g = grid_cells(nx, ny);
+    return (int64_t)g.x * g.y;
+}
+
+hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel<4>, dim3(1), dim3(256), 0, s, partials,
+                       count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize1(const double *partials, int64_t count, double *out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel<1>, dim3(1), dim3(256), 0, s, partials,
+                       count, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_macro(const MacroArgs<T> &a, hipStream_t s) {
+    hipLaunchKernelGGL(macro_kernel<T>, grid_cells(a.nx, a.ny), dim3(64, 4), 0,
+                       s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mass(const MacroArgs<T> &a, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(mass_kernel<T>, grid_cells(a.nx, a.ny), dim3(64, 4), 0,
+                       s, a, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_boundary(const MacroArgs<T> &a, const int32_t *y0,
+                           const int32_t *y1, int n_out, double *out,
+                           hipStream_t s) {
+    const int threads = n_out + 1;
+    hipLaunchKernelGGL(boundary_kernel<T>, dim3((threads + 63) / 64), dim3(64),
+                       0, s, a, y0, y1, n_out, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_cells(const uint8_t *types, uint16_t *cell, int nx,
+                              int ny, int pitch, hipStream_t s) {
+    hipLaunchKernelGGL(build_cells_kernel, grid_cells(pitch, ny), dim3(64, 4),
+                       0, s, types, cell, nx, ny, pitch);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_rest_cells<float>(float *f, size_t plane, const int32_t *cells,
+                                    int count, int nx, int pitch, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_cells_kernel<float>, dim3((count + 255) / 256),
+                       dim3(256), 0, s, f, plane, cells, count, nx, pitch);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t launch_rest_all<float>(float *f, size_t plane, hipStream_t s) {
+    const size_t count = 9 * plane;
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(fill_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       f, count, 0.0f);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_export_plane(const T *f, const uint16_t *cell, double *out,
+                               int i, int nx, int ny, int pitch, size_t plane,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(export_plane_kernel<T>, grid_cells(nx, ny), dim3(64, 4),
+                       0, s, f, cell, out, i, nx, ny, pitch, plane);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_import_plane(T *f, const uint16_t *cell, const double *in,
+                               int i, int nx, int ny, int pitch, size_t plane,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(import_plane_kernel<T>, grid_cells(nx, ny), dim3(64, 4),
+                       0, s, f, cell, in, i, nx, ny, pitch, plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const KeysArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(keys_kernel, grid_cells(a.nx, a.ny), dim3(64, 4), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const uint64_t *key, const uint64_t *hash,
+                       const int32_t *idx, int64_t count, int64_t k_eff,
+                       int32_t *sel, hipStream_t s) {
+    if (count <= 0 || k_eff <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((count + 255) / 256)),
+                       dim3(256), 0, s, key, hash, idx, count, k_eff, sel);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip(uint8_t *types, const int32_t *removed,
+                       const int32_t *added, int k_eff, double *mass_out,
+                       const double *rho, hipStream_t s) {
+    if (k_eff <= 0) return hipSuccess;
+    hipLaunchKernelGGL(removed_mass_kernel, dim3(1), dim3(64), 0, s, rho,
+                       removed, k_eff, mass_out);
+    hipLaunchKernelGGL(flip_kernel, dim3((k_eff + 255) / 256), dim3(256), 0, s,
+                       types, removed, added, k_eff);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
+                             unsigned long long *out, hipStream_t s) {
+    size_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(count_type_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       s, types, count, which, out);
+    return hipGetLastError();
+}
+
+// Single-precision instantiations (double precision: lbm_f64.hip).
+template hipError_t launch_sweep<float>(const SweepArgs<float> &, bool, hipStream_t);
+template hipError_t launch_macro<float>(const MacroArgs<float> &, hipStream_t);
+template hipError_t launch_mass<float>(const MacroArgs<float> &, double *, hipStream_t);
+template hipError_t launch_boundary<float>(const MacroArgs<float> &, const int32_t *,
+                                           const int32_t *, int, double *, hipStream_t);
+template hipError_t launch_export_plane<float>(const float *, const uint16_t *, double *,
+                                               int, int, int, int, size_t, hipStream_t);
+template hipError_t launch_import_plane<float>(float *, const uint16_t *, const double *,
+                                               int, int, int, int, size_t, hipStream_t);
+
+}  // namespace lbm

@@ -1,0 +1,306 @@
+"""ctypes binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function here forwards to the HIP library liblbm.so built in this
+package directory; none computes anything itself.  If the library is missing
+the first call raises: there is no fallback path.
+
+PyTorch is only used to supply the HIP stream (torch.cuda.current_stream) and,
+optionally, device memory; the library owns its own buffers.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblbm.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "lbm.h")
+
+LBM_OK, LBM_NOT_CONVERGED = 0, 1
+LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE = -1, -2, -3, -4
+LBM_SOLID, LBM_FLUID, LBM_INLET, LBM_OUTLET = 0, 1, 2, 3
+LBM_F64, LBM_F32 = 0, 1
+LBM_WARM, LBM_COLD = 0, 1
+LBM_CRIT_PAPER, LBM_CRIT_SPEED = 0, 1
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+class lbm_geometry_desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("widths", ctypes.c_int32 * 9), ("tau", ctypes.c_double),
+                ("u_peak", ctypes.c_double), ("rho_out", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lbm_stats(ctypes.Structure):
+    _fields_ = [("n_outlets", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_fluid", ctypes.c_int64), ("n_nonsolid", ctypes.c_int64),
+                ("flow_in", ctypes.c_double), ("dp", ctypes.c_double),
+                ("theta", ctypes.c_double), ("dg", ctypes.c_double),
+                ("flow_ave", ctypes.c_double), ("mass", ctypes.c_double),
+                ("residual", ctypes.c_double), ("steps", ctypes.c_int64)]
+
+
+class lbm_shape_params(ctypes.Structure):
+    _fields_ = [("frac", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("band_x", ctypes.c_int32), ("band_y", ctypes.c_int32),
+                ("criterion", ctypes.c_int32), ("reinit", ctypes.c_int32)]
+
+
+class lbm_shape_result(ctypes.Structure):
+    _fields_ = [("k_eff", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_cand_fluid", ctypes.c_int64), ("n_cand_solid", ctypes.c_int64),
+                ("n_fluid_before", ctypes.c_int64), ("n_fluid_after", ctypes.c_int64),
+                ("mass_removed", ctypes.c_double), ("mass_added", ctypes.c_double)]
+
+
+_lib = None
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions include/lbm.h declares."""
+    txt = open(HEADER_PATH).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", txt)))
+
+
+def load() -> ctypes.CDLL:
+    """Load liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    H = ctypes.c_void_p
+    sig = {
+        "lbm_create_geometry": (ctypes.c_int, [P, P, P, ctypes.POINTER(H)]),
+        "lbm_run_to_steady": (ctypes.c_int, [H, i64, f64, i32, P, P]),
+        "lbm_outlet_stats": (ctypes.c_int, [H, P, i32, P]),
+        "lbm_shape_update": (ctypes.c_int, [H, P, P, P]),
+        "lbm_last_exchange": (ctypes.c_int, [H, P, P, i32]),
+        "lbm_get_mask": (ctypes.c_int, [H, P, sz]),
+        "lbm_get_macro": (ctypes.c_int, [H, P, P, P, sz]),
+        "lbm_get_state": (ctypes.c_int, [H, P, sz]),
+        "lbm_set_state": (ctypes.c_int, [H, P, sz]),
+        "lbm_footprint_bytes": (sz, [P]),
+        "lbm_destroy": (None, [H]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+        "lbm_bench_sweep": (ctypes.c_int, [H, i32, P]),
+        "lbm_profile_sweeps": (ctypes.c_int, [H, i32, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise LbmError(rc, load().lbm_last_error().decode())
+    return rc
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def current_stream_handle():
+    """hipStream_t of torch's current stream (None without a GPU)."""
+    import torch
+    if not torch.cuda.is_available():
+        return None
+    return torch.cuda.current_stream().cuda_stream
+
+
+def make_desc(nx, ny, tau, u_peak, rho_out=1.0, precision=LBM_F64, levels=0, widths=None):
+    d = lbm_geometry_desc()
+    d.nx, d.ny, d.levels = int(nx), int(ny), int(levels)
+    for k, w in enumerate(widths or []):
+        d.widths[k] = int(w)
+    d.tau, d.u_peak, d.rho_out = float(tau), float(u_peak), float(rho_out)
+    d.precision = int(precision)
+    d.reserved = 0
+    return d
+
+
+def lbm_create_geometry(desc: lbm_geometry_desc, cell_types: np.ndarray | None = None,
+                        hip_stream=None):
+    lib = load()
+    h = ctypes.c_void_p()
+    types_ptr = None
+    if cell_types is not None:
+        cell_types = np.ascontiguousarray(cell_types, np.uint8)
+        if cell_types.shape != (desc.ny, desc.nx):
+            raise ValueError("cell_types must have shape (ny, nx)")
+        types_ptr = _p(cell_types)
+    _check(lib.lbm_create_geometry(ctypes.byref(desc), types_ptr, hip_stream, ctypes.byref(h)))
+    return h
+
+
+def lbm_run_to_steady(h, max_steps: int, tol: float = 0.0, check_every: int = 100):
+    """Returns (status, steps_done, residual); status LBM_OK,
+    LBM_NOT_CONVERGED or LBM_EUNSTABLE (the latter is returned, not raised)."""
+    lib = load()
+    steps = ctypes.c_int64(0)
+    res = ctypes.c_double(0.0)
+    rc = lib.lbm_run_to_steady(h, int(max_steps), float(tol), int(check_every),
+                               ctypes.byref(steps), ctypes.byref(res))
+    if rc < 0 and rc != LBM_EUNSTABLE:
+        _check(rc)
+    return rc, steps.value, res.value
+
+
+def lbm_outlet_stats(h, flow_cap: int = 1024):
+    lib = load()
+    flow = np.zeros(max(flow_cap, 1), np.float64)
+    s = lbm_stats()
+    _check(lib.lbm_outlet_stats(h, _p(flow), int(flow_cap), ctypes.byref(s)))
+    return flow[:s.n_outlets].copy(), s
+
+
+def make_shape_params(frac=0.01, seed=0, band_x=2, band_y=1, criterion=LBM_CRIT_PAPER,
+                      reinit=LBM_WARM):
+    p = lbm_shape_params()
+    p.frac, p.seed = float(frac), int(seed) & (2 ** 64 - 1)
+    p.band_x, p.band_y, p.criterion, p.reinit = int(band_x), int(band_y), int(criterion), int(reinit)
+    return p
+
+
+def lbm_shape_update(h, params: lbm_shape_params, rho_ux_uy=None):
+    lib = load()
+    r = lbm_shape_result()
+    ptr = None
+    if rho_ux_uy is not None:
+        arr = np.ascontiguousarray(np.stack([np.asarray(a, np.float64) for a in rho_ux_uy]))
+        ptr = _p(arr)
+    _check(lib.lbm_shape_update(h, ctypes.byref(params), ptr, ctypes.byref(r)))
+    return r
+
+
+def lbm_last_exchange(h, cap: int):
+    lib = load()
+    rem = np.zeros(max(cap, 1), np.int64)
+    add = np.zeros(max(cap, 1), np.int64)
+    k = _check(lib.lbm_last_exchange(h, _p(rem), _p(add), int(cap)))
+    return rem[:k].copy(), add[:k].copy()
+
+
+def lbm_get_mask(h, nx: int, ny: int) -> np.ndarray:
+    out = np.zeros((ny, nx), np.uint8)
+    _check(load().lbm_get_mask(h, _p(out), out.size))
+    return out
+
+
+def lbm_get_macro(h, nx: int, ny: int):
+    rho = np.zeros((ny, nx))
+    ux = np.zeros((ny, nx))
+    uy = np.zeros((ny, nx))
+    _check(load().lbm_get_macro(h, _p(rho), _p(ux), _p(uy), rho.size))
+    return rho, ux, uy
+
+
+def lbm_get_state(h, nx: int, ny: int) -> np.ndarray:
+    f = np.zeros((9, ny, nx))
+    _check(load().lbm_get_state(h, _p(f), f.size))
+    return f
+
+
+def lbm_set_state(h, f: np.ndarray) -> None:
+    f = np.ascontiguousarray(f, np.float64)
+    _check(load().lbm_set_state(h, _p(f), f.size))
+
+
+def lbm_footprint_bytes(desc: lbm_geometry_desc) -> int:
+    return int(load().lbm_footprint_bytes(ctypes.byref(desc)))
+
+
+def lbm_destroy(h) -> None:
+    if h:
+        load().lbm_destroy(h)
+
+
+def lbm_last_error() -> str:
+    return load().lbm_last_error().decode()
+
+
+def lbm_bench_sweep(h, steps: int) -> float:
+    ms = ctypes.c_double(0.0)
+    _check(load().lbm_bench_sweep(h, int(steps), ctypes.byref(ms)))
+    return ms.value
+
+
+def lbm_profile_sweeps(h, enable: bool):
+    """Returns (launches, total_ms) recorded so far."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(load().lbm_profile_sweeps(h, int(bool(enable)), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+class Lattice:
+    """Owning wrapper of one handle."""
+
+    def __init__(self, types: np.ndarray | None, tau: float, u_peak: float, rho_out: float = 1.0,
+                 precision: int = LBM_F64, nx: int | None = None, ny: int | None = None,
+                 levels: int = 0, widths=None, stream=None):
+        if types is not None:
+            ny, nx = types.shape
+        self.nx, self.ny = int(nx), int(ny)
+        self.desc = make_desc(self.nx, self.ny, tau, u_peak, rho_out, precision, levels, widths)
+        if stream is None:
+            stream = current_stream_handle()
+        self.h = lbm_create_geometry(self.desc, types, stream)
+
+    def close(self):
+        if self.h:
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, max_steps, tol=0.0, check_every=100):
+        return lbm_run_to_steady(self.h, max_steps, tol, check_every)
+
+    def stats(self, flow_cap=1024):
+        return lbm_outlet_stats(self.h, flow_cap)
+
+    def shape_update(self, frac=0.01, seed=0, band_x=2, band_y=1, criterion=LBM_CRIT_PAPER,
+                     reinit=LBM_WARM, field=None):
+        p = make_shape_params(frac, seed, band_x, band_y, criterion, reinit)
+        r = lbm_shape_update(self.h, p, field)
+        rem, add = lbm_last_exchange(self.h, max(r.k_eff, 1))
+        return r, rem, add
+
+    def mask(self):
+        return lbm_get_mask(self.h, self.nx, self.ny)
+
+    def macro(self):
+        return lbm_get_macro(self.h, self.nx, self.ny)
+
+    def state(self):
+        return lbm_get_state(self.h, self.nx, self.ny)
+
+    def set_state(self, f):
+        lbm_set_state(self.h, f)
+
+    def bench_sweep(self, steps):
+        return lbm_bench_sweep(self.h, steps)
+
+    def profile_sweeps(self, enable):
+        return lbm_profile_sweeps(self.h, enable)

@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every symbol include/lbm.h declares
+(no device calls: runs without a GPU)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_1303_0107_amd import lbm
+
+EXPECTED = {
+    "lbm_create_geometry", "lbm_run_to_steady", "lbm_outlet_stats", "lbm_shape_update",
+    "lbm_last_exchange", "lbm_get_mask", "lbm_get_macro", "lbm_get_state", "lbm_set_state",
+    "lbm_footprint_bytes", "lbm_destroy", "lbm_last_error", "lbm_bench_sweep",
+    "lbm_profile_sweeps",
+}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_1303_0107_amd import _build
+        _build.build()
+    return lbm.load()
+
+
+def test_header_declares_the_boundary():
+    assert set(lbm.declared_functions()) == EXPECTED
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in lbm.declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header():
+    # sizes implied by the header's field lists (natural alignment, x86-64)
+    assert ctypes.sizeof(lbm.lbm_geometry_desc) == 4 * 12 + 3 * 8 + 8
+    assert ctypes.sizeof(lbm.lbm_stats) == 8 + 16 + 7 * 8 + 8
+    assert ctypes.sizeof(lbm.lbm_shape_params) == 8 + 8 + 16
+    assert ctypes.sizeof(lbm.lbm_shape_result) == 8 + 32 + 16
+
+
+def test_footprint_and_validation_need_no_device(lib):
+    d = lbm.make_desc(1024, 512, 0.6, 0.04, precision=lbm.LBM_F32)
+    fp = lbm.lbm_footprint_bytes(d)
+    # two buffers of nine float planes dominate
+    assert fp >= 2 * 9 * 1024 * 512 * 4
+    bad = lbm.make_desc(1024, 512, 0.5, 0.04)
+    assert lbm.lbm_footprint_bytes(bad) == 0
+    bad = lbm.make_desc(2, 512, 0.6, 0.04)
+    assert lbm.lbm_footprint_bytes(bad) == 0
+
+
+def test_invalid_descriptor_is_rejected_before_any_device_call(lib):
+    d = lbm.make_desc(64, 32, 0.4, 0.04)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create_geometry(d, None, None)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert "tau" in lbm.lbm_last_error()
