@@ -8,11 +8,13 @@ lattice is brought from rest to steady state (untimed).
 
 value  = lattice updates per second over the timed steps (all nx*ny cells,
          MLUPS), whole-job wall time between two device synchronisations.
-roofline: the sweep kernel, algorithmic bytes per launch
+roofline: the sweep kernel.  Algorithmic bytes per time step
          = 18 * s * N_nonsolid + N  (each non-solid population read and
-         written once, s bytes each, plus one cell byte per cell), divided by
-         the mean launch-to-launch time of the plain sweeps inside the timed
-         region, measured with HIP events on the handle's stream.
+         written once, s bytes each, plus one cell byte per cell); a launch
+         advances steps_per_launch steps, so bytes per launch = that times
+         the per-step figure.  Divided by the mean launch time of the sweeps
+         inside the timed region, measured with HIP events recorded on the
+         handle's stream around each residual-check interval's launches.
 cpu_baseline: the FP64 oracle on the same lattice, a bounded number of steps.
 """
 from __future__ import annotations
@@ -29,6 +31,15 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS + % HBM roofline (D2Q9 1024x512); p50/p99 solve latency, mixed load"
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per time step of the plain sweep launches, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size) of this
+# build's kernels; profiles/sweep_tb_float_distributor-1024x512.txt.  Keyed by
+# (workload, storage precision, kernel); reported as null for anything else
+# and must be re-measured whenever the kernel changes.
+MEASURED_TRAFFIC_PER_STEP = {
+    ("distributor-1024x512-L3", "f32", "tb_kernel"): 14.902e6 / 8,
+}
 
 
 def workloads():
@@ -142,14 +153,19 @@ def main() -> int:
               f"theta={st.theta:.6f} dg={st.dg:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launches, sweep_ms = lat.profile_sweeps(False)
+    timed_steps, launches, sweep_ms = lat.profile_sweeps(False)
 
     mlups = N * sweeps / wall / 1e6
-    bytes_per_launch = 18 * s_bytes * nns + N
+    bytes_per_step = 18 * s_bytes * nns + N
+    steps_per_launch = timed_steps / max(launches, 1)
+    bytes_per_launch = bytes_per_step * steps_per_launch
     avg_ms = sweep_ms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     n, res, flow, st, r = last
     spread = float((flow.max() - flow.min()) / flow.mean()) if len(flow) else 0.0
+    kernel = "tb_kernel" if steps_per_launch > 1.0 else "step_kernel"
+    per_step = MEASURED_TRAFFIC_PER_STEP.get((w.name, args.precision, kernel))
+    traffic = round(per_step * steps_per_launch) if per_step else None
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -174,9 +190,10 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"sweep_kernel<{'float' if s_bytes == 4 else 'double'},false>",
-            "bytes_per_launch": bytes_per_launch, "launches": launches,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": kernel + f" ({'float' if s_bytes == 4 else 'double'} storage)",
+            "bytes_per_step": bytes_per_step, "steps_per_launch": round(steps_per_launch, 3),
+            "bytes_per_launch": round(bytes_per_launch), "launches": launches,
             "avg_launch_us": round(avg_ms * 1e3, 3),
             "copy_ceiling_GBs": round(copy_gbs, 1),
             "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),

@@ -218,17 +218,19 @@ const char *lbm_last_error(void);
 /* Advance the lattice by `steps` time steps without residual checks and
  * report the mean time per step in milliseconds, measured with HIP events
  * recorded on the handle's stream before the first and after the last
- * sweep launch.  The steps are real: the state advances. */
+ * sweep launch.  The steps are real: the state advances (by steps plus up to
+ * 128 untimed warm-up steps that build the launch graphs first). */
 int lbm_bench_sweep(lbm_handle *h, int32_t steps, double *ms_per_step);
 
 /* Sweep timing inside lbm_run_to_steady.  enable = 1 resets the counters
  * and starts recording: each residual-check interval then records a HIP
  * event on the handle's stream before its first sweep launch and after its
- * last plain (non-check) sweep launch, and adds the elapsed time and the
- * number of plain sweeps in between.  enable = 0 stops recording.  Either
- * way the current totals are returned (launches, total_ms may be NULL). */
-int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *launches,
-                       double *total_ms);
+ * last one, and adds the elapsed time, the time steps and the sweep kernel
+ * launches in between (a launch may advance several steps).  enable = 0
+ * stops recording.  Either way the current totals are returned (any of
+ * steps, launches, total_ms may be NULL). */
+int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *steps,
+                       int64_t *launches, double *total_ms);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -223,9 +224,32 @@ struct lbm_handle {
     int64_t prof_launches = 0;
     double prof_ms = 0.0;
 
+    // Replayable runs of plain sweeps, keyed by (starting buffer, count).
+    struct Graph {
+        int parity;
+        int64_t n;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t capture_stream = nullptr;
+    bool use_graphs = true;
+
+    // Temporal blocking: tiles holding at least one non-solid cell.
+    bool use_tb = true;
+    DeviceBuffer tiles;
+    std::vector<int32_t> tile_host;
+    int n_tiles = 0;
+    int64_t prof_kernels = 0;
+
     size_t N() const { return (size_t)nx * ny; }
     size_t esize() const { return elem_size(precision); }
+    void drop_graphs() {
+        for (Graph &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
     ~lbm_handle() {
+        drop_graphs();
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
         if (pinned) (void)hipHostFree(pinned);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -233,6 +257,16 @@ struct lbm_handle {
 };
 
 namespace {
+
+int tile_width(int precision) { return precision == LBM_F64 ? tile_w<double>() : tile_w<float>(); }
+int tile_height(int precision) { return precision == LBM_F64 ? tile_h<double>() : tile_h<float>(); }
+int steps_per_launch(int precision) {
+    return precision == LBM_F64 ? TbShape<double>::halo : TbShape<float>::halo;
+}
+size_t tile_count(int nx, int ny, int precision) {
+    const int w = tile_width(precision), hh = tile_height(precision);
+    return (size_t)((nx + w - 1) / w) * ((ny + hh - 1) / hh);
+}
 
 size_t footprint(int nx, int ny, int precision) {
     const int pitch = pitch_for(nx);
@@ -243,7 +277,9 @@ size_t footprint(int nx, int ny, int precision) {
     b += N;                                  // type map
     b += (size_t)ny * es;                    // inlet profile
     b += 2 * plane * es;                     // u_prev
-    b += (size_t)sweep_blocks(nx, ny) * 4 * sizeof(double);
+    const size_t ntiles = tile_count(nx, ny, precision);
+    b += std::max((size_t)sweep_blocks(nx, ny), ntiles) * 4 * sizeof(double);
+    b += ntiles * sizeof(int32_t);
     b += 3 * N * sizeof(double);             // macro field (exchange step)
     return b;
 }
@@ -268,6 +304,31 @@ void compute_ports(lbm_handle *h) {
         h->n_fluid += v == LBM_FLUID;
         h->n_nonsolid += v != LBM_SOLID;
     }
+}
+
+// Tiles of the temporal-blocking sweep whose cells include a non-solid one,
+// packed as (tile row << 16 | tile column), uploaded to the device.
+void rebuild_tiles(lbm_handle *h) {
+    const int kTileW = tile_width(h->precision), kTileH = tile_height(h->precision);
+    const int ntx = (h->nx + kTileW - 1) / kTileW, nty = (h->ny + kTileH - 1) / kTileH;
+    h->tile_host.clear();
+    for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) {
+            bool any = false;
+            for (int y = ty * kTileH; y < std::min(h->ny, (ty + 1) * kTileH) && !any; ++y)
+                for (int x = tx * kTileW; x < std::min(h->nx, (tx + 1) * kTileW); ++x)
+                    if (h->host_types[(size_t)y * h->nx + x] != LBM_SOLID) {
+                        any = true;
+                        break;
+                    }
+            if (any) h->tile_host.push_back((ty << 16) | tx);
+        }
+    h->n_tiles = (int)h->tile_host.size();
+    h->tiles.ensure((size_t)ntx * nty * sizeof(int32_t));
+    if (h->n_tiles > 0)
+        HIP_TRY(hipMemcpyAsync(h->tiles.p, h->tile_host.data(), h->n_tiles * sizeof(int32_t),
+                               hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
 }
 
 // Parabolic inlet profile (Sec. 3.3) on each maximal run of inlet rows,
@@ -343,6 +404,79 @@ void step(lbm_handle *h, bool check) {
     h->cur = 1 - h->cur;
 }
 
+// `n` plain sweeps.  Runs of 8 or more are captured once per (starting
+// buffer, n) into a HIP graph of kernel nodes on a private stream and then
+// replayed on the handle's stream, which removes the per-launch host cost
+// from the time loop.  LBM_GRAPHS=0 in the environment launches directly.
+template <typename T>
+void plain_sweeps(lbm_handle *h, int64_t n) {
+    constexpr int64_t kMaxGraph = 128;
+    while (n > 0) {
+        const int64_t m = std::min(n, kMaxGraph);
+        n -= m;
+        if (!h->use_graphs || m < 8) {
+            for (int64_t s = 0; s < m; ++s) step<T>(h, false);
+            continue;
+        }
+        hipGraphExec_t exec = nullptr;
+        for (const auto &g : h->graphs)
+            if (g.parity == h->cur && g.n == m) exec = g.exec;
+        if (!exec) {
+            if (h->graphs.size() >= 16) h->drop_graphs();
+            if (!h->capture_stream)
+                HIP_TRY(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+            const int parity = h->cur;
+            hipStream_t user = h->stream;
+            HIP_TRY(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+            h->stream = h->capture_stream;
+            hipError_t err = hipSuccess;
+            for (int64_t s = 0; s < m && err == hipSuccess; ++s) {
+                err = launch_sweep<T>(sweep_args<T>(h, false), false, h->stream);
+                h->cur = 1 - h->cur;
+            }
+            h->stream = user;
+            h->cur = parity;
+            hipGraph_t graph = nullptr;
+            const hipError_t end = hipStreamEndCapture(h->capture_stream, &graph);
+            HIP_TRY(err);
+            HIP_TRY(end);
+            const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIP_TRY(inst);
+            h->graphs.push_back({parity, m, exec});
+        }
+        HIP_TRY(hipGraphLaunch(exec, h->stream));
+        if (m % 2) h->cur = 1 - h->cur;
+    }
+}
+
+// Advance `n` >= 1 steps; with `check` the last step also writes residual
+// partials (per tile or per sweep block; see partial_count).
+template <typename T>
+void advance(lbm_handle *h, int64_t n, bool check) {
+    if (h->use_tb) {
+        while (n > 0) {
+            const int s = (int)std::min<int64_t>(n, steps_per_launch(h->precision));
+            n -= s;
+            HIP_TRY(launch_tb<T>(sweep_args<T>(h, check && n == 0), h->tiles.as<int32_t>(),
+                                 h->n_tiles, s, check && n == 0, h->stream));
+            h->cur = 1 - h->cur;
+            ++h->prof_kernels;
+        }
+        return;
+    }
+    plain_sweeps<T>(h, check ? n - 1 : n);
+    h->prof_kernels += check ? n - 1 : n;
+    if (check) {
+        step<T>(h, true);
+        ++h->prof_kernels;
+    }
+}
+
+int64_t partial_count(const lbm_handle *h) {
+    return h->use_tb ? h->n_tiles : sweep_blocks(h->nx, h->ny);
+}
+
 template <typename T>
 void uprev_from_state(lbm_handle *h) {
     MacroArgs<T> a = macro_args<T>(h);
@@ -373,7 +507,7 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
              int64_t *steps_done, double *residual) {
     ensure_pinned(h, 64 * sizeof(double));
     uprev_from_state<T>(h);
-    const int64_t nblocks = sweep_blocks(h->nx, h->ny);
+    const int64_t nparts = partial_count(h);
     double *red = h->red.as<double>();
     int64_t done = 0;
     double r = h->last_residual;
@@ -381,12 +515,12 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
     bool converged = false;
     while (done < max_steps) {
         const int64_t chunk = std::min<int64_t>(k, max_steps - done);
-        const bool timed = h->profiling && chunk > 1;
+        const bool timed = h->profiling;
+        const int64_t k0 = h->prof_kernels;
         if (timed) HIP_TRY(hipEventRecord(h->ev[0], h->stream));
-        for (int64_t s = 0; s + 1 < chunk; ++s) step<T>(h, false);
+        advance<T>(h, chunk, true);
         if (timed) HIP_TRY(hipEventRecord(h->ev[1], h->stream));
-        step<T>(h, true);
-        HIP_TRY(launch_finalize4(h->partials.as<double>(), nblocks, red, h->stream));
+        HIP_TRY(launch_finalize4(h->partials.as<double>(), nparts, red, h->stream));
         HIP_TRY(hipMemcpyAsync(h->pinned, red, 4 * sizeof(double),
                                hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -396,7 +530,9 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
             h->prof_ms += ms;
-            h->prof_launches += chunk - 1;
+            h->prof_launches += chunk;
+        } else {
+            h->prof_kernels = k0;
         }
         const double num = h->pinned[0], den = h->pinned[1], bad = h->pinned[3];
         if (bad != 0.0 || !std::isfinite(num) || !std::isfinite(den)) {
@@ -517,6 +653,10 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         h->u_peak = d->u_peak;
         h->rho_out = d->rho_out;
         h->stream = static_cast<hipStream_t>(hip_stream);
+        const char *g = std::getenv("LBM_GRAPHS");
+        h->use_graphs = !(g && g[0] == '0');
+        const char *tb = std::getenv("LBM_TB");
+        h->use_tb = !(tb && tb[0] == '0');
         HIP_TRY(hipGetDevice(&h->device));
         if (cell_types) {
             if (!check_types(h->nx, h->ny, cell_types, why)) {
@@ -535,7 +675,9 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         h->types.ensure(h->N());
         h->uin.ensure((size_t)h->ny * es);
         h->uprev.ensure(2 * h->plane * es);
-        h->partials.ensure((size_t)sweep_blocks(h->nx, h->ny) * 4 * sizeof(double));
+        const size_t ntiles = tile_count(h->nx, h->ny, h->precision);
+        h->partials.ensure(std::max((size_t)sweep_blocks(h->nx, h->ny), ntiles) * 4 *
+                           sizeof(double));
         h->red.ensure(64 * sizeof(double));
         const int n_out = (int)h->out_y0.size();
         h->out_rows.ensure(2 * (size_t)std::max(n_out, 1) * sizeof(int32_t));
@@ -563,6 +705,7 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         }
         HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
                                    h->ny, h->pitch, h->stream));
+        rebuild_tiles(h);
         HIP_TRY(hipStreamSynchronize(h->stream));
     } catch (const std::bad_alloc &) {
         delete h;
@@ -609,19 +752,23 @@ int lbm_bench_sweep(lbm_handle *h, int32_t steps, double *ms_per_step) {
         HIP_TRY(hipSetDevice(h->device));
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
+        // warm the graph cache and kernel setup outside the timed region
+        const int64_t warm = std::min<int64_t>(steps, 128);
+        if (h->precision == LBM_F64)
+            advance<double>(h, warm, false);
+        else
+            advance<float>(h, warm, false);
         HIP_TRY(hipEventRecord(e0, h->stream));
-        for (int s = 0; s < steps; ++s) {
-            if (h->precision == LBM_F64)
-                step<double>(h, false);
-            else
-                step<float>(h, false);
-        }
+        if (h->precision == LBM_F64)
+            advance<double>(h, steps, false);
+        else
+            advance<float>(h, steps, false);
         HIP_TRY(hipEventRecord(e1, h->stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
         *ms_per_step = (double)ms / steps;
-        h->steps += steps;
+        h->steps += steps + warm;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         return LBM_OK;
@@ -632,8 +779,8 @@ int lbm_bench_sweep(lbm_handle *h, int32_t steps, double *ms_per_step) {
     }
 }
 
-int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *launches,
-                       double *total_ms) {
+int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *steps,
+                       int64_t *launches, double *total_ms) {
     g_error.clear();
     if (!h) return fail(LBM_EINVAL, "null handle");
     try {
@@ -642,13 +789,15 @@ int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *launches,
             for (hipEvent_t &e : h->ev)
                 if (!e) HIP_TRY(hipEventCreate(&e));
             h->prof_launches = 0;
+            h->prof_kernels = 0;
             h->prof_ms = 0.0;
         }
         h->profiling = enable != 0;
     } catch (const HipFail &e) {
         return guard_hip(e);
     }
-    if (launches) *launches = h->prof_launches;
+    if (steps) *steps = h->prof_launches;
+    if (launches) *launches = h->prof_kernels;
     if (total_ms) *total_ms = h->prof_ms;
     return LBM_OK;
 }
@@ -846,6 +995,7 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
         }
         h->last_removed.assign(rem.begin(), rem.end());
         h->last_added.assign(add.begin(), add.end());
+        if (keff > 0) rebuild_tiles(h);
         r->k_eff = (int32_t)keff;
         r->n_fluid_after = nf_after;
         r->mass_removed = mass_removed;

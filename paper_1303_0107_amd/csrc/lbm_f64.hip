@@ -15,6 +15,8 @@
 
 #pragma clang fp contract(off)
 
+#include "lbm_sweep.h"
+
 namespace lbm {
 namespace f64 {
 
@@ -56,46 +58,34 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
         for (int k = 0; k < NV; ++k) v[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
 }
 
-template <bool CHECK>
-__global__ __launch_bounds__(256) void sweep_kernel(SweepArgs<double> a) {
-    const int lx = threadIdx.x, ly = threadIdx.y;
-    const int x = blockIdx.x * 64 + lx;
-    const int y = blockIdx.y * 4 + ly;
-    const bool in = x < a.nx && y < a.ny;
-    const size_t n = (size_t)(in ? y : 0) * a.pitch + (in ? x : 0);
-    const uint32_t cw = in ? a.cell[n] : 0u;
-    const uint32_t type = cw >> 8;
-    const bool active = in && type != kSolid;
-    double part[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active) {
-        const size_t P = a.plane;
-        double f[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const bool wall = i > 0 && ((cw >> (i - 1)) & 1u);
-            const size_t src =
-                wall ? (size_t)kOpp[i] * P + n
-                     : (size_t)i * P + n - kCx[i] - (ptrdiff_t)kCy[i] * a.pitch;
-            f[i] = a.fin[src];
-        }
+// One cell of one time step on full populations: Zou-He closure on inlet
+// (velocity u_in, unknowns 1, 5, 8) and outlet cells (density rho_out, zero
+// transverse velocity, unknowns 3, 6, 7), moments (Eq. 2), relaxation
+// f - (1/tau)(f - feq) (Eq. 1) to the equilibrium of Sec. 2.1.
+struct Cell {
+    using T = double;
+    using CT = double;
+    __device__ static __forceinline__ void update(double (&f)[9], uint32_t type, double uin,
+                                                  const SweepArgs<double> &a, double &mass,
+                                                  double &ux, double &uy) {
         if (type == kInlet) {
-            const double ux = a.uin[y];
-            const double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7])) / (1.0 - ux);
-            const double ru = rho * ux;
+            const double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7])) / (1.0 - uin);
+            const double ru = rho * uin;
             f[1] = f[3] + (2.0 / 3.0) * ru;
             f[5] = f[7] - 0.5 * (f[2] - f[4]) + (1.0 / 6.0) * ru;
             f[8] = f[6] + 0.5 * (f[2] - f[4]) + (1.0 / 6.0) * ru;
         } else if (type == kOutlet) {
-            const double ux =
+            const double uo =
                 -1.0 + (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8])) / a.rho_out;
-            const double ru = a.rho_out * ux;
+            const double ru = a.rho_out * uo;
             f[3] = f[1] - (2.0 / 3.0) * ru;
             f[7] = f[5] + 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * ru;
             f[6] = f[8] - 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * ru;
         }
         double r, mx, my;
         moments(f, r, mx, my);
-        const double ux = mx / r, uy = my / r;
+        ux = mx / r;
+        uy = my / r;
         const double uu = ux * ux + uy * uy;
         const double om = a.omega;
 #pragma unroll
@@ -103,29 +93,11 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepArgs<double> a) {
             const double cu = kCx[i] * ux + kCy[i] * uy;
             const double feq =
                 weight(i) * r * (1.0 + cu * 3.0 + 0.5 * (cu * cu) * 9.0 - 0.5 * uu * 3.0);
-            a.fout[(size_t)i * a.plane + n] = f[i] - om * (f[i] - feq);
+            f[i] = f[i] - om * (f[i] - feq);
         }
-        if (CHECK) {
-            const double px = a.uprev[n], py = a.uprev[a.plane + n];
-            const double dx = ux - px, dy = uy - py;
-            part[0] = dx * dx + dy * dy;
-            part[1] = ux * ux + uy * uy;
-            part[2] = r;
-            part[3] = (isfinite(r) && isfinite(ux) && isfinite(uy)) ? 0.0 : 1.0;
-            a.uprev[n] = ux;
-            a.uprev[a.plane + n] = uy;
-        }
+        mass = r;
     }
-    if (CHECK) {
-        const int tid = ly * 64 + lx;
-        block_sum<4>(part, tid);
-        if (tid == 0) {
-            const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) a.partials[b * 4 + k] = part[k];
-        }
-    }
-}
+};
 
 __global__ __launch_bounds__(256) void macro_kernel(MacroArgs<double> a) {
     const int x = blockIdx.x * 64 + threadIdx.x;
@@ -264,14 +236,16 @@ static inline dim3 grid_cells(int ncols, int ny) {
 }
 
 template <>
-hipError_t launch_sweep<double>(const SweepArgs<double> &a, bool check,
-                                hipStream_t s) {
-    const dim3 g = grid_cells(a.nx, a.ny), b(64, 4);
-    if (check)
-        hipLaunchKernelGGL(f64::sweep_kernel<true>, g, b, 0, s, a);
-    else
-        hipLaunchKernelGGL(f64::sweep_kernel<false>, g, b, 0, s, a);
-    return hipGetLastError();
+hipError_t launch_sweep<double>(const SweepArgs<double> &a, bool check, hipStream_t s) {
+    return sweep::launch_step<f64::Cell>(a, check, s);
+}
+
+template <>
+hipError_t launch_tb<double>(const SweepArgs<double> &a, const int32_t *tiles, int n_tiles,
+                             int steps, bool check, hipStream_t s) {
+    return sweep::launch_tb<f64::Cell, TbShape<double>::rows, TbShape<double>::halo,
+                             TbShape<double>::threads, true>(a, tiles, n_tiles, steps,
+                                                                     check, s);
 }
 
 template <>

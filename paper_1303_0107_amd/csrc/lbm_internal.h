@@ -52,6 +52,42 @@ struct KeysArgs {
 
 template <typename T>
 hipError_t launch_sweep(const SweepArgs<T> &a, bool check, hipStream_t s);
+
+// Temporal blocking: regions of 64 x rows cells with a halo of `halo` cells
+// (so up to `halo` steps per launch), tiles of (64 - 2 halo) x (rows - 2 halo)
+// cells, `threads` threads per workgroup, two LDS copies of the region
+// (9 * 64 * rows * sizeof(T) bytes each).
+template <typename T>
+struct TbShape;
+#ifndef LBM_TB32_ROWS
+#define LBM_TB32_ROWS 32
+#endif
+#ifndef LBM_TB32_HALO
+#define LBM_TB32_HALO 8
+#endif
+#ifndef LBM_TB64_ROWS
+#define LBM_TB64_ROWS 16
+#endif
+#ifndef LBM_TB64_HALO
+#define LBM_TB64_HALO 4
+#endif
+template <>
+struct TbShape<float> {
+    static constexpr int rows = LBM_TB32_ROWS, halo = LBM_TB32_HALO, threads = 1024;
+};
+template <>
+struct TbShape<double> {
+    static constexpr int rows = LBM_TB64_ROWS, halo = LBM_TB64_HALO, threads = 1024;
+};
+template <typename T>
+constexpr int tile_w() { return 64 - 2 * TbShape<T>::halo; }
+template <typename T>
+constexpr int tile_h() { return TbShape<T>::rows - 2 * TbShape<T>::halo; }
+// `steps` (1..TbShape<T>::halo) time steps on the listed tiles; with `check` the last
+// step also writes per-tile residual partials (4 doubles per tile).
+template <typename T>
+hipError_t launch_tb(const SweepArgs<T> &a, const int32_t *tiles, int n_tiles, int steps,
+                     bool check, hipStream_t s);
 int64_t sweep_blocks(int nx, int ny);
 hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
                             hipStream_t s);
@@ -96,6 +132,9 @@ hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
 template <>
 hipError_t launch_sweep<double>(const SweepArgs<double> &a, bool check, hipStream_t s);
 template <>
+hipError_t launch_tb<double>(const SweepArgs<double> &a, const int32_t *tiles, int n_tiles,
+                             int steps, bool check, hipStream_t s);
+template <>
 hipError_t launch_macro<double>(const MacroArgs<double> &a, hipStream_t s);
 template <>
 hipError_t launch_mass<double>(const MacroArgs<double> &a, double *partials, hipStream_t s);
@@ -116,6 +155,11 @@ hipError_t launch_import_plane<double>(double *f, const uint16_t *cell, const do
                                        int i, int nx, int ny, int pitch, size_t plane,
                                        hipStream_t s);
 // Single-precision specialisations, defined in lbm_kernels.hip.
+template <>
+hipError_t launch_sweep<float>(const SweepArgs<float> &a, bool check, hipStream_t s);
+template <>
+hipError_t launch_tb<float>(const SweepArgs<float> &a, const int32_t *tiles, int n_tiles,
+                            int steps, bool check, hipStream_t s);
 template <>
 hipError_t launch_rest_cells<float>(float *f, size_t plane, const int32_t *cells,
                                     int count, int nx, int pitch, hipStream_t s);

@@ -21,6 +21,7 @@
 #include <stdint.h>
 
 #include "lbm_internal.h"
+#include "lbm_sweep.h"
 
 namespace lbm {
 
@@ -75,62 +76,45 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid,
 }
 
 // ---------------------------------------------------------------------------
-// One time step (Eq. 1): pull streaming with halfway bounce-back, Zou-He
-// boundaries on inlet / outlet cells, moments (Eq. 2), BGK relaxation to the
-// second-order equilibrium.  With CHECK the step also accumulates, per
-// block, sum |u - u_prev|^2, sum |u|^2, sum rho and the number of non-finite
-// cells, and stores u as the new u_prev.
 #ifndef LBM_F32_COMPUTE
 #define LBM_F32_COMPUTE double
 #endif
+#ifndef LBM_F32_POLY
+#define LBM_F32_POLY LBM_F32_COMPUTE
+#endif
 
-// Single-precision storage, arithmetic in CT (double by default: with float
-// storage the rounding of the arithmetic, not of the stored offsets,
-// dominates the error of steady fields).  Every sum pairs the populations
-// that a reflection y -> -y exchanges (2<->4, 5<->8, 6<->7), and every
-// product is formed so that such a reflection maps it to itself or to its
-// exact negative: on a mirror-symmetric lattice the computed flow is then
-// mirror-symmetric bit for bit, and rounding cannot feed the slow
-// antisymmetric mode (the flux split between the two halves of a tree).
-template <typename T, bool CHECK, typename CT = LBM_F32_COMPUTE>
-__global__ __launch_bounds__(256) void sweep_kernel(SweepArgs<T> a) {
-    const int lx = threadIdx.x;                  // 0..63
-    const int ly = threadIdx.y;                  // 0..3
-    const int x = blockIdx.x * 64 + lx;
-    const int y = blockIdx.y * 4 + ly;
-    const bool in = x < a.nx && y < a.ny;
-    const size_t n = (size_t)(in ? y : 0) * a.pitch + (in ? x : 0);
-    const uint32_t cw = in ? a.cell[n] : 0u;
-    const uint32_t type = cw >> 8;
-    const bool active = in && type != kSolid;
-
-    double part[4] = {0.0, 0.0, 0.0, 0.0};
-    if (active) {
-        const size_t P = a.plane;
-        CT d[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const bool wall = i > 0 && ((cw >> (i - 1)) & 1u);
-            const size_t src =
-                wall ? (size_t)kOpp[i] * P + n
-                     : (size_t)i * P + n - kCx[i] - (ptrdiff_t)kCy[i] * a.pitch;
-            d[i] = (CT)a.fin[src];
-        }
+// One cell of one time step on single-precision offsets d_i = f_i - w_i,
+// arithmetic in CT (double by default: with float storage the rounding of
+// the arithmetic, not of the stored offsets, dominates the error of steady
+// fields).  Zou-He closure on inlet (velocity u_in, unknowns 1, 5, 8) and
+// outlet cells (density rho_out, zero transverse velocity, unknowns 3, 6, 7),
+// moments (Eq. 2), BGK relaxation (Eq. 1) to the equilibrium of Sec. 2.1
+// written for offsets: feq_i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2
+// - 1.5 u.u)).  Every sum pairs the populations that a reflection y -> -y
+// exchanges (2<->4, 5<->8, 6<->7) and every product maps to itself or its
+// exact negative under it, so on a mirror-symmetric lattice the computed
+// flow is mirror-symmetric bit for bit.  Multiply-adds are fused only inside
+// one expression, as written, so every kernel that inlines this function
+// rounds identically.
+struct F32Cell {
+    using T = float;
+    using CT = LBM_F32_COMPUTE;
+    __device__ static __forceinline__ void update(CT (&d)[9], uint32_t type, CT uin,
+                                                  const SweepArgs<float> &a, double &mass,
+                                                  double &ux_out, double &uy_out) {
+#pragma clang fp contract(on)
         if (type == kInlet) {
-            // velocity (u_in(y), 0) imposed; unknowns 1, 5, 8
-            const CT ux = (CT)a.uin[y];
             const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[3] + (d[6] + d[7]));
-            const CT dr = (s + ux) / (CT(1) - ux);
-            const CT ru = (CT(1) + dr) * ux;
+            const CT dr = (s + uin) / (CT(1) - uin);
+            const CT ru = (CT(1) + dr) * uin;
             const CT h = CT(0.5) * (d[2] - d[4]);
             d[1] = d[3] + (CT(2) / CT(3)) * ru;
             d[5] = d[7] - h + (CT(1) / CT(6)) * ru;
             d[8] = d[6] + h + (CT(1) / CT(6)) * ru;
         } else if (type == kOutlet) {
-            // density rho_out and zero transverse velocity; unknowns 3, 6, 7
             const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[1] + (d[5] + d[8]));
-            const CT ux = (s + (CT)a.one_minus_rho_out) / (CT)a.rho_out;
-            const CT ru = (CT)a.rho_out * ux;
+            const CT uo = (s + (CT)a.one_minus_rho_out) / (CT)a.rho_out;
+            const CT ru = (CT)a.rho_out * uo;
             const CT h = CT(0.5) * (d[2] - d[4]);
             d[3] = d[1] - (CT(2) / CT(3)) * ru;
             d[7] = d[5] + h - (CT(1) / CT(6)) * ru;
@@ -142,40 +126,35 @@ __global__ __launch_bounds__(256) void sweep_kernel(SweepArgs<T> a) {
         const CT jy = (d[2] + (d[5] + d[6])) - (d[4] + (d[8] + d[7]));
         const CT ir = CT(1) / rho;
         const CT ux = jx * ir, uy = jy * ir;
-        const CT uu15 = CT(1.5) * (ux * ux + uy * uy);
         const CT om = (CT)a.omega;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const CT cu = CT(kCx[i]) * ux + CT(kCy[i]) * uy;
-            const CT deq =
-                wgt<CT>(i) * (dr + rho * (CT(3) * cu + CT(4.5) * cu * cu - uu15));
-            a.fout[(size_t)i * a.plane + n] = (T)(d[i] + om * (deq - d[i]));
-        }
-        if (CHECK) {
-            const size_t m = (size_t)y * a.pitch + x;
-            const double px = (double)a.uprev[m];
-            const double py = (double)a.uprev[a.plane + m];
-            const double dx = (double)ux - px, dy = (double)uy - py;
-            part[0] = dx * dx + dy * dy;
-            part[1] = (double)ux * (double)ux + (double)uy * (double)uy;
-            part[2] = 1.0 + (double)dr;
-            const bool fin = isfinite((double)rho) && isfinite((double)ux) &&
-                             isfinite((double)uy);
-            part[3] = fin ? 0.0 : 1.0;
-            a.uprev[m] = (T)ux;
-            a.uprev[a.plane + m] = (T)uy;
-        }
+        // Opposite directions i, opp(i) have c.u = +-cu: their equilibrium
+        // offsets share the even part A = 4.5 cu^2 - 1.5 u.u and differ in the
+        // sign of the odd part B = 3 cu.
+        // The velocity polynomials (magnitude ~0.1) are formed in PT; their
+        // rounding enters the offsets multiplied by w_i rho and stays well
+        // below the float storage rounding of the offsets themselves.
+        using PT = LBM_F32_POLY;
+        const PT pux = (PT)ux, puy = (PT)uy;
+        const PT puu15 = PT(1.5) * (pux * pux + puy * puy);
+        auto relax_pair = [&](int i, int j, PT cu, CT w) {
+            const PT A = PT(4.5) * cu * cu - puu15;
+            const PT B = PT(3) * cu;
+            const CT ei = w * (dr + rho * (CT)(A + B));
+            const CT ej = w * (dr + rho * (CT)(A - B));
+            d[i] = d[i] + om * (ei - d[i]);
+            d[j] = d[j] + om * (ej - d[j]);
+        };
+        const CT w0 = CT(4) / CT(9), w1 = CT(1) / CT(9), w5 = CT(1) / CT(36);
+        d[0] = d[0] + om * (w0 * (dr - rho * (CT)puu15) - d[0]);
+        relax_pair(1, 3, pux, w1);
+        relax_pair(2, 4, puy, w1);
+        relax_pair(5, 7, pux + puy, w5);
+        relax_pair(6, 8, puy - pux, w5);
+        mass = 1.0 + (double)dr;
+        ux_out = (double)ux;
+        uy_out = (double)uy;
     }
-    if (CHECK) {
-        const int tid = ly * 64 + lx;
-        block_sum<4>(part, tid, 256);
-        if (tid == 0) {
-            const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) a.partials[b * 4 + k] = part[k];
-        }
-    }
-}
+};
 
 // Sum `count` groups of NV doubles in a fixed order (one block of 256).
 template <int NV>
@@ -545,14 +524,17 @@ static inline dim3 grid_cells(int ncols, int ny) {
     return dim3((unsigned)((ncols + 63) / 64), (unsigned)((ny + 3) / 4));
 }
 
-template <typename T>
-hipError_t launch_sweep(const SweepArgs<T> &a, bool check, hipStream_t s) {
-    const dim3 g = grid_cells(a.nx, a.ny), b(64, 4);
-    if (check)
-        hipLaunchKernelGGL((sweep_kernel<T, true>), g, b, 0, s, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel<T, false>), g, b, 0, s, a);
-    return hipGetLastError();
+template <>
+hipError_t launch_sweep<float>(const SweepArgs<float> &a, bool check, hipStream_t s) {
+    return sweep::launch_step<F32Cell>(a, check, s);
+}
+
+template <>
+hipError_t launch_tb<float>(const SweepArgs<float> &a, const int32_t *tiles, int n_tiles,
+                            int steps, bool check, hipStream_t s) {
+    return sweep::launch_tb<F32Cell, TbShape<float>::rows, TbShape<float>::halo,
+                             TbShape<float>::threads, true>(a, tiles, n_tiles, steps,
+                                                                   check, s);
 }
 
 int64_t sweep_blocks(int nx, int ny) {
@@ -679,7 +661,6 @@ hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
 }
 
 // Single-precision instantiations (double precision: lbm_f64.hip).
-template hipError_t launch_sweep<float>(const SweepArgs<float> &, bool, hipStream_t);
 template hipError_t launch_macro<float>(const MacroArgs<float> &, hipStream_t);
 template hipError_t launch_mass<float>(const MacroArgs<float> &, double *, hipStream_t);
 template hipError_t launch_boundary<float>(const MacroArgs<float> &, const int32_t *,

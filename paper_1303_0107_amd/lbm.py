@@ -96,7 +96,7 @@ def load() -> ctypes.CDLL:
         "lbm_destroy": (None, [H]),
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_bench_sweep": (ctypes.c_int, [H, i32, P]),
-        "lbm_profile_sweeps": (ctypes.c_int, [H, i32, P, P]),
+        "lbm_profile_sweeps": (ctypes.c_int, [H, i32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -242,11 +242,13 @@ def lbm_bench_sweep(h, steps: int) -> float:
 
 
 def lbm_profile_sweeps(h, enable: bool):
-    """Returns (launches, total_ms) recorded so far."""
+    """Returns (steps, kernel launches, total_ms) recorded so far."""
     n = ctypes.c_int64(0)
+    k = ctypes.c_int64(0)
     ms = ctypes.c_double(0.0)
-    _check(load().lbm_profile_sweeps(h, int(bool(enable)), ctypes.byref(n), ctypes.byref(ms)))
-    return n.value, ms.value
+    _check(load().lbm_profile_sweeps(h, int(bool(enable)), ctypes.byref(n), ctypes.byref(k),
+                                     ctypes.byref(ms)))
+    return n.value, k.value, ms.value
 
 
 class Lattice:

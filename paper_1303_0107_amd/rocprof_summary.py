@@ -1,0 +1,66 @@
+"""Condense rocprofv3 CSV output into the short text summaries kept here.
+
+usage: python -m paper_1303_0107_amd.rocprof_summary STATS_CSV [FETCH_CSV WRITE_CSV] --cmd "..." --kernel SUBSTR
+           [--copy-bytes N] [--algo-bytes N]
+
+STATS_CSV is a --kernel-trace --stats *_kernel_stats.csv; FETCH_CSV/WRITE_CSV
+are --pmc FETCH_SIZE / WRITE_SIZE *_counter_collection.csv files of the same
+program.  The counters are scaled by what they read for the plain copy kernel
+(__amd_rocclr_copyBuffer of --copy-bytes bytes, reads and writes each).
+"""
+import argparse
+import collections
+import csv
+
+
+def per_kernel(path, counter):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            agg[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("stats")
+    ap.add_argument("fetch", nargs="?")
+    ap.add_argument("write", nargs="?")
+    ap.add_argument("--cmd", required=True)
+    ap.add_argument("--pmc-cmd", default="")
+    ap.add_argument("--kernel", required=True)
+    ap.add_argument("--copy-bytes", type=int, default=1 << 28)
+    ap.add_argument("--algo-bytes", type=int, default=0)
+    a = ap.parse_args()
+    print(f"command: {a.cmd}")
+    print()
+    print(f"{'kernel':70s} {'calls':>8s} {'avg_us':>9s} {'total_ms':>10s} {'pct':>6s}")
+    for r in csv.DictReader(open(a.stats)):
+        print(f"{r['Name'][:70]:70s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.3f} "
+              f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}")
+    if not a.fetch:
+        return
+    print()
+    print(f"counters: {a.pmc_cmd}")
+    fetch, nf = per_kernel(a.fetch, "FETCH_SIZE")
+    write, nw = per_kernel(a.write, "WRITE_SIZE")
+    kib = 1024.0
+    copy_f = max(v for (k, g), v in fetch.items() if "copyBuffer" in k)
+    copy_w = max(v for (k, g), v in write.items() if "copyBuffer" in k)
+    sf = a.copy_bytes / (copy_f * kib)
+    sw = a.copy_bytes / (copy_w * kib)
+    print(f"plain copy of {a.copy_bytes} B: FETCH_SIZE {copy_f:.1f} KiB, WRITE_SIZE {copy_w:.1f} KiB"
+          f" -> scale fetch x{sf:.3f}, write x{sw:.3f}")
+    for (k, g), v in sorted(fetch.items(), key=lambda kv: -kv[1]):
+        if a.kernel in k:
+            w = write.get((k, g), 0.0)
+            fb, wb = v * kib * sf, w * kib * sw
+            line = (f"{k[:70]} grid {g}: dispatches {nf[(k, g)]}, fetch {fb / 1e6:.3f} MB, "
+                    f"write {wb / 1e6:.3f} MB, traffic {(fb + wb) / 1e6:.3f} MB per dispatch")
+            if a.algo_bytes:
+                line += f" ({(fb + wb) / a.algo_bytes:.3f} x algorithmic {a.algo_bytes / 1e6:.3f} MB)"
+            print(line)
+
+
+if __name__ == "__main__":
+    main()

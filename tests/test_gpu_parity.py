@@ -502,6 +502,64 @@ def test_invalid_requests():
         g.shape_update(field=(rho, ux, uy))
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_graph_replay_matches_direct_launches(prec, monkeypatch):
+    """Runs of plain sweeps replayed from captured HIP graphs (the default)
+    give the same bits as direct launches, replay after replay with eager
+    check steps and host synchronisations in between."""
+    wl = I.CORRECTNESS_128x64
+    t = wl.types()
+    out = []
+    for mode in ("1", "0"):
+        monkeypatch.setenv("LBM_GRAPHS", mode)
+        g = lbm.Lattice(t, wl.tau, wl.u_peak, precision=prec)
+        states = []
+        for _ in range(4):
+            g.run(250, 0.0, 50)       # 5 chunks: graph of 49 sweeps + check step
+            states.append(g.state())
+        g.bench_sweep(300)            # graphs of 128 + remainder
+        states.append(g.state())
+        out.append(states)
+        g.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", [(200, 70), (130, 37)])
+def test_temporal_blocking_matches_single_steps(prec, shape, monkeypatch):
+    """The temporally blocked sweep (several steps per launch through LDS)
+    and one launch per step produce the same bits, across exchange steps
+    (which change the tile list) and chunk lengths that are not multiples of
+    the steps per launch."""
+    nx, ny = shape
+    t = I.channel(nx, ny)
+    rng = np.random.default_rng(nx)
+    inner = t[2:-2, 3:-3]
+    inner[rng.random(inner.shape) < 0.1] = 0
+    res = []
+    for mode in ("1", "0"):
+        monkeypatch.setenv("LBM_TB", mode)
+        g = lbm.Lattice(t, 0.7, 0.04, precision=prec)
+        out = []
+        g.run(203, 0.0, 37)
+        out.append(g.state())
+        out.append(g.run(157, 1e-12, 50)[2])
+        r, rem, add = g.shape_update(frac=0.02, seed=9)
+        g.run(121, 0.0, 7)
+        out += [g.state(), g.mask(), g.stats()[0]]
+        g.bench_sweep(77)
+        out.append(g.state())
+        res.append(out)
+        g.close()
+    a, b = res
+    for x, y in zip(a, b):
+        if isinstance(x, float):
+            assert x == pytest.approx(y, rel=1e-12)   # residual sums are grouped differently
+        else:
+            assert np.array_equal(x, y)
+
+
 def test_bitwise_deterministic():
     wl = I.CORRECTNESS_128x64
     t = wl.types()
