@@ -89,7 +89,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed optimisation iterations")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--precision", choices=["f32", "f64", "f16", "bf16"], default="f32",
+                    help="population storage (f64: double storage and arithmetic; f32: float "
+                         "storage, double arithmetic; f16/bf16: 16-bit storage, float arithmetic)")
     ap.add_argument("--workload", default="distributor-1024x512-L3")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cap", type=int, default=200000, help="step cap per solve")
@@ -117,8 +119,10 @@ def main() -> int:
     types = w.types()
     N = types.size
     nns = int(np.count_nonzero(types))
-    prec = lbm.LBM_F32 if args.precision == "f32" else lbm.LBM_F64
-    s_bytes = 4 if prec == lbm.LBM_F32 else 8
+    prec = {"f64": lbm.LBM_F64, "f32": lbm.LBM_F32, "f16": lbm.LBM_F32_S_F16,
+            "bf16": lbm.LBM_F32_S_BF16}[args.precision]
+    s_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[args.precision]
+    arith = "f64" if args.precision in ("f64", "f32") else "f32"
     frac = w.extra.get("frac", 0.01)
     k = 100
 
@@ -177,11 +181,11 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": arith,
         "data": "synthetic",
         "config": {
             "workload": w.name, "nx": w.nx, "ny": w.ny, "non_solid_cells": nns,
-            "tau": w.tau, "u_peak": w.u_peak, "precision": args.precision,
+            "tau": w.tau, "u_peak": w.u_peak, "storage": args.precision, "arithmetic": arith,
             "step": f"exchange (frac {frac}) + solve to r<{args.tol:g} (cap {args.cap}, "
                     f"check every {k}) + outlet stats",
             "sweeps_timed": sweeps, "mflups": round(nns * sweeps / wall / 1e6, 2),
@@ -191,7 +195,7 @@ def main() -> int:
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kernel + f" ({'float' if s_bytes == 4 else 'double'} storage)",
+            "kernel": kernel + f" ({args.precision} storage)",
             "bytes_per_step": bytes_per_step, "steps_per_launch": round(steps_per_launch, 3),
             "bytes_per_launch": round(bytes_per_launch), "launches": launches,
             "avg_launch_us": round(avg_ms * 1e3, 3),

@@ -56,11 +56,17 @@ extern "C" {
 #define LBM_OUTLET 3
 
 /* ---- precision forms ------------------------------------------------------
- * LBM_F64: populations stored and relaxed in double precision.
- * LBM_F32: populations stored as float offsets f_i - w_i, relaxed in float.
- * Reductions (mass, fluxes, pressure drop, residual) are double in both. */
+ * LBM_F64:        populations f_i stored and relaxed in double precision, in
+ *                 the reference operation order (bitwise reproducible).
+ * LBM_F32:        offsets f_i - w_i stored in float, relaxed in double.
+ * LBM_F32_S_F16:  offsets stored in IEEE half precision, relaxed in float.
+ * LBM_F32_S_BF16: offsets stored in bfloat16, relaxed in float.
+ * Reductions (mass, fluxes, pressure drop, residual, exchange keys) are
+ * double in every form. */
 #define LBM_F64 0
 #define LBM_F32 1
+#define LBM_F32_S_F16 2
+#define LBM_F32_S_BF16 3
 
 /* ---- exchange-step options --------------------------------------------- */
 #define LBM_WARM 0        /* new fluid cells start at rest, rest is kept    */
@@ -79,7 +85,7 @@ typedef struct {
     double tau;         /* BGK relaxation time, > 1/2 (tau = 3 nu + 1/2)  */
     double u_peak;      /* peak of the parabolic inlet profile (lattice u)*/
     double rho_out;     /* density imposed on outlet cells, > 0           */
-    int32_t precision;  /* LBM_F64 or LBM_F32                             */
+    int32_t precision;  /* LBM_F64, LBM_F32, LBM_F32_S_F16, LBM_F32_S_BF16 */
     int32_t reserved;   /* must be 0                                      */
 } lbm_geometry_desc;
 

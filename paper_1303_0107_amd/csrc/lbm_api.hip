@@ -71,7 +71,22 @@ struct DeviceBuffer {
 int pitch_for(int nx) { return (nx + 63) / 64 * 64; }
 
 size_t elem_size(int precision) {
-    return precision == LBM_F64 ? sizeof(double) : sizeof(float);
+    switch (precision) {
+        case LBM_F64: return sizeof(double);
+        case LBM_F32: return sizeof(float);
+        default: return 2;  // 16-bit storage forms
+    }
+}
+
+// Call f with a value of the storage type of `precision`.
+template <class F>
+decltype(auto) with_storage(int precision, F &&f) {
+    switch (precision) {
+        case LBM_F64: return f(double{});
+        case LBM_F32: return f(float{});
+        case LBM_F32_S_F16: return f(h16{});
+        default: return f(bf16{});
+    }
 }
 
 // Flat arborescent distributor: the same construction as the input
@@ -166,7 +181,8 @@ bool check_desc(const lbm_geometry_desc *d, std::string &why) {
         why = "|u_peak| must be < 1";
         return false;
     }
-    if (d->precision != LBM_F64 && d->precision != LBM_F32) {
+    if (d->precision != LBM_F64 && d->precision != LBM_F32 && d->precision != LBM_F32_S_F16 &&
+        d->precision != LBM_F32_S_BF16) {
         why = "unknown precision";
         return false;
     }
@@ -215,6 +231,7 @@ struct lbm_handle {
     size_t pinned_bytes = 0;
 
     std::vector<uint8_t> host_types;
+    std::vector<float> uin_f;
     std::vector<int32_t> out_y0, out_y1;
     int64_t n_fluid = 0, n_nonsolid = 0, steps = 0;
     double last_residual = std::nan("");
@@ -258,10 +275,14 @@ struct lbm_handle {
 
 namespace {
 
-int tile_width(int precision) { return precision == LBM_F64 ? tile_w<double>() : tile_w<float>(); }
-int tile_height(int precision) { return precision == LBM_F64 ? tile_h<double>() : tile_h<float>(); }
+int tile_width(int precision) {
+    return with_storage(precision, [](auto t) { return tile_w<decltype(t)>(); });
+}
+int tile_height(int precision) {
+    return with_storage(precision, [](auto t) { return tile_h<decltype(t)>(); });
+}
 int steps_per_launch(int precision) {
-    return precision == LBM_F64 ? TbShape<double>::halo : TbShape<float>::halo;
+    return with_storage(precision, [](auto t) { return TbShape<decltype(t)>::halo; });
 }
 size_t tile_count(int nx, int ny, int precision) {
     const int w = tile_width(precision), hh = tile_height(precision);
@@ -275,8 +296,8 @@ size_t footprint(int nx, int ny, int precision) {
     size_t b = 2 * 9 * plane * es;           // populations
     b += plane * sizeof(uint16_t);           // cell words
     b += N;                                  // type map
-    b += (size_t)ny * es;                    // inlet profile
-    b += 2 * plane * es;                     // u_prev
+    b += (size_t)ny * sizeof(double);        // inlet profile
+    b += 2 * plane * sizeof(double);         // u_prev
     const size_t ntiles = tile_count(nx, ny, precision);
     b += std::max((size_t)sweep_blocks(nx, ny), ntiles) * 4 * sizeof(double);
     b += ntiles * sizeof(int32_t);
@@ -371,8 +392,8 @@ SweepArgs<T> sweep_args(lbm_handle *h, bool check) {
     a.fin = h->f[h->cur].as<T>();
     a.fout = h->f[1 - h->cur].as<T>();
     a.cell = h->cell.as<uint16_t>();
-    a.uin = h->uin.as<T>();
-    a.uprev = check ? h->uprev.as<T>() : nullptr;
+    a.uin = h->uin.as<UinT<T>>();
+    a.uprev = check ? h->uprev.as<double>() : nullptr;
     a.partials = check ? h->partials.as<double>() : nullptr;
     a.nx = h->nx;
     a.ny = h->ny;
@@ -480,7 +501,7 @@ int64_t partial_count(const lbm_handle *h) {
 template <typename T>
 void uprev_from_state(lbm_handle *h) {
     MacroArgs<T> a = macro_args<T>(h);
-    a.uprev = h->uprev.as<T>();
+    a.uprev = h->uprev.as<double>();
     HIP_TRY(launch_macro<T>(a, h->stream));
 }
 
@@ -496,10 +517,7 @@ void macro_to_device(lbm_handle *h) {
 }
 
 void macro_dispatch(lbm_handle *h) {
-    if (h->precision == LBM_F64)
-        macro_to_device<double>(h);
-    else
-        macro_to_device<float>(h);
+    with_storage(h->precision, [&](auto t) { macro_to_device<decltype(t)>(h); });
 }
 
 template <typename T>
@@ -673,8 +691,8 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         for (int b = 0; b < 2; ++b) h->f[b].ensure(9 * h->plane * es);
         h->cell.ensure(h->plane * sizeof(uint16_t));
         h->types.ensure(h->N());
-        h->uin.ensure((size_t)h->ny * es);
-        h->uprev.ensure(2 * h->plane * es);
+        h->uin.ensure((size_t)h->ny * sizeof(double));
+        h->uprev.ensure(2 * h->plane * sizeof(double));
         const size_t ntiles = tile_count(h->nx, h->ny, h->precision);
         h->partials.ensure(std::max((size_t)sweep_blocks(h->nx, h->ny), ntiles) * 4 *
                            sizeof(double));
@@ -692,17 +710,18 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
                                    n_out * sizeof(int32_t), hipMemcpyHostToDevice,
                                    h->stream));
         }
+        // inlet velocities: double for the double form, float otherwise (the
+        // offset forms read them through their arithmetic type)
         const std::vector<double> u = inlet_profile(h);
         if (h->precision == LBM_F64) {
             HIP_TRY(hipMemcpyAsync(h->uin.p, u.data(), h->ny * sizeof(double),
                                    hipMemcpyHostToDevice, h->stream));
-            reset_all<double>(h);
         } else {
-            std::vector<float> uf(u.begin(), u.end());
-            HIP_TRY(hipMemcpyAsync(h->uin.p, uf.data(), h->ny * sizeof(float),
+            h->uin_f.assign(u.begin(), u.end());
+            HIP_TRY(hipMemcpyAsync(h->uin.p, h->uin_f.data(), h->ny * sizeof(float),
                                    hipMemcpyHostToDevice, h->stream));
-            reset_all<float>(h);
         }
+        with_storage(h->precision, [&](auto t) { reset_all<decltype(t)>(h); });
         HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
                                    h->ny, h->pitch, h->stream));
         rebuild_tiles(h);
@@ -734,9 +753,9 @@ int lbm_run_to_steady(lbm_handle *h, int64_t max_steps, double tol,
         return fail(LBM_EINVAL, "max_steps >= 0 and check_every >= 1 required");
     try {
         HIP_TRY(hipSetDevice(h->device));
-        if (h->precision == LBM_F64)
-            return run_impl<double>(h, max_steps, tol, check_every, steps_done, residual);
-        return run_impl<float>(h, max_steps, tol, check_every, steps_done, residual);
+        return with_storage(h->precision, [&](auto t) {
+            return run_impl<decltype(t)>(h, max_steps, tol, check_every, steps_done, residual);
+        });
     } catch (const HipFail &e) {
         return guard_hip(e);
     } catch (const std::bad_alloc &) {
@@ -754,15 +773,9 @@ int lbm_bench_sweep(lbm_handle *h, int32_t steps, double *ms_per_step) {
         HIP_TRY(hipEventCreate(&e1));
         // warm the graph cache and kernel setup outside the timed region
         const int64_t warm = std::min<int64_t>(steps, 128);
-        if (h->precision == LBM_F64)
-            advance<double>(h, warm, false);
-        else
-            advance<float>(h, warm, false);
+        with_storage(h->precision, [&](auto t) { advance<decltype(t)>(h, warm, false); });
         HIP_TRY(hipEventRecord(e0, h->stream));
-        if (h->precision == LBM_F64)
-            advance<double>(h, steps, false);
-        else
-            advance<float>(h, steps, false);
+        with_storage(h->precision, [&](auto t) { advance<decltype(t)>(h, steps, false); });
         HIP_TRY(hipEventRecord(e1, h->stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -819,10 +832,7 @@ int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
     double mass = 0.0;
     try {
         HIP_TRY(hipSetDevice(h->device));
-        if (h->precision == LBM_F64)
-            stats_impl<double>(h, b, mass);
-        else
-            stats_impl<float>(h, b, mass);
+        with_storage(h->precision, [&](auto t) { stats_impl<decltype(t)>(h, b, mass); });
     } catch (const HipFail &e) {
         return guard_hip(e);
     } catch (const std::bad_alloc &) {
@@ -955,13 +965,10 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
             HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, mass_out, m,
                                 h->stream));
             if (p->reinit == LBM_WARM) {
-                if (h->precision == LBM_F64) {
-                    zero_cells<double>(h, srem, (int)keff);
-                    zero_cells<double>(h, sadd, (int)keff);
-                } else {
-                    zero_cells<float>(h, srem, (int)keff);
-                    zero_cells<float>(h, sadd, (int)keff);
-                }
+                with_storage(h->precision, [&](auto t) {
+                    zero_cells<decltype(t)>(h, srem, (int)keff);
+                    zero_cells<decltype(t)>(h, sadd, (int)keff);
+                });
             }
             HIP_TRY(hipMemcpyAsync(rem.data(), srem, keff * sizeof(int32_t),
                                    hipMemcpyDeviceToHost, h->stream));
@@ -973,10 +980,7 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
             mass_removed = h->pinned[0];
         }
         if (p->reinit == LBM_COLD) {
-            if (h->precision == LBM_F64)
-                reset_all<double>(h);
-            else
-                reset_all<float>(h);
+            with_storage(h->precision, [&](auto t) { reset_all<decltype(t)>(h); });
         }
         HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
                                    h->ny, h->pitch, h->stream));
@@ -1064,10 +1068,7 @@ int lbm_get_state(lbm_handle *h, double *f, size_t n) {
     if (!h || !f || n < 9 * h->N()) return fail(LBM_EINVAL, "bad arguments");
     try {
         HIP_TRY(hipSetDevice(h->device));
-        if (h->precision == LBM_F64)
-            export_state<double>(h, f);
-        else
-            export_state<float>(h, f);
+        with_storage(h->precision, [&](auto t) { export_state<decltype(t)>(h, f); });
     } catch (const HipFail &e) {
         return guard_hip(e);
     } catch (const std::bad_alloc &) {
@@ -1081,10 +1082,7 @@ int lbm_set_state(lbm_handle *h, const double *f, size_t n) {
     if (!h || !f || n < 9 * h->N()) return fail(LBM_EINVAL, "bad arguments");
     try {
         HIP_TRY(hipSetDevice(h->device));
-        if (h->precision == LBM_F64)
-            import_state<double>(h, f);
-        else
-            import_state<float>(h, f);
+        with_storage(h->precision, [&](auto t) { import_state<decltype(t)>(h, f); });
         h->steps = 0;
         h->last_residual = std::nan("");
     } catch (const HipFail &e) {

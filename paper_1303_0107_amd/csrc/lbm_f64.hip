@@ -65,6 +65,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
 struct Cell {
     using T = double;
     using CT = double;
+    __device__ static __forceinline__ double load(double v) { return v; }
+    __device__ static __forceinline__ double store(double v) { return v; }
     __device__ static __forceinline__ void update(double (&f)[9], uint32_t type, double uin,
                                                   const SweepArgs<double> &a, double &mass,
                                                   double &ux, double &uy) {

@@ -1,25 +1,78 @@
 // Internal declarations shared by the kernels and the host library.
 #pragma once
 
+#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 namespace lbm {
 
 enum : uint32_t { kSolid = 0, kFluid = 1, kInlet = 2, kOutlet = 3 };
 enum : int { kCritPaper = 0, kCritSpeed = 1 };
 
+// 16-bit storage types of the reduced-precision forms.
+using h16 = _Float16;
+using bf16 = __hip_bfloat16;
+
+// Conversions between a storage type and double / float (round to nearest
+// even where the target is narrower).
+template <typename T>
+struct Sto;
+template <>
+struct Sto<double> {
+    __device__ static __forceinline__ double to_d(double v) { return v; }
+    __device__ static __forceinline__ double from_d(double v) { return v; }
+};
+template <>
+struct Sto<float> {
+    __device__ static __forceinline__ double to_d(float v) { return (double)v; }
+    __device__ static __forceinline__ float from_d(double v) { return (float)v; }
+    __device__ static __forceinline__ float to_f(float v) { return v; }
+    __device__ static __forceinline__ float from_f(float v) { return v; }
+};
+// float -> IEEE binary16 with the hardware conversion (round to nearest
+// even).  The empty register-only asm statement makes the float value opaque,
+// so the compiler cannot fold the conversion into a preceding multiply-add
+// (a fused multiply-add rounding once, directly to half): every kernel then
+// rounds to float first and to half second, and stores the same bits.
+__device__ __forceinline__ h16 f32_to_h16_rne(float f) {
+    asm volatile("" : "+v"(f));
+    return (h16)f;
+}
+
+template <>
+struct Sto<h16> {
+    __device__ static __forceinline__ double to_d(h16 v) { return (double)(float)v; }
+    __device__ static __forceinline__ h16 from_d(double v) { return f32_to_h16_rne((float)v); }
+    __device__ static __forceinline__ float to_f(h16 v) { return (float)v; }
+    __device__ static __forceinline__ h16 from_f(float v) { return f32_to_h16_rne(v); }
+};
+template <>
+struct Sto<bf16> {
+    __device__ static __forceinline__ double to_d(bf16 v) { return (double)__bfloat162float(v); }
+    __device__ static __forceinline__ bf16 from_d(double v) { return __float2bfloat16((float)v); }
+    __device__ static __forceinline__ float to_f(bf16 v) { return __bfloat162float(v); }
+    __device__ static __forceinline__ bf16 from_f(float v) { return __float2bfloat16(v); }
+};
+
 // Arguments of one sweep launch.  Populations live in nine planes of `plane`
 // elements (ny rows of `pitch`).  Single precision stores the offsets
 // d_i = f_i - w_i; double precision stores f_i (see lbm_f64.hip).
+// Inlet velocities are double for the double form and float for the offset
+// forms (never 16-bit: the imposed velocity keeps its precision).
+template <typename T>
+using UinT = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
+
 template <typename T>
 struct SweepArgs {
     const T *fin;
     T *fout;
     const uint16_t *cell;
-    const T *uin;      // inlet velocity per row
-    T *uprev;          // two planes (u_x, u_y); check steps only
+    const UinT<T> *uin;  // inlet velocity per row
+    double *uprev;     // two planes (u_x, u_y); check steps only
     double *partials;  // 4 doubles per block; check steps only
     int nx, ny, pitch;
     size_t plane;
@@ -33,7 +86,7 @@ struct MacroArgs {
     const T *f;
     const uint16_t *cell;
     double *rho, *ux, *uy;  // logical layout, optional
-    T *uprev;               // pitched, optional
+    double *uprev;          // pitched, optional
     int nx, ny, pitch;
     size_t plane;
 };
@@ -78,6 +131,14 @@ struct TbShape<float> {
 template <>
 struct TbShape<double> {
     static constexpr int rows = LBM_TB64_ROWS, halo = LBM_TB64_HALO, threads = 1024;
+};
+template <>
+struct TbShape<h16> {
+    static constexpr int rows = 32, halo = 8, threads = 1024;
+};
+template <>
+struct TbShape<bf16> {
+    static constexpr int rows = 32, halo = 8, threads = 1024;
 };
 template <typename T>
 constexpr int tile_w() { return 64 - 2 * TbShape<T>::halo; }
@@ -154,16 +215,21 @@ template <>
 hipError_t launch_import_plane<double>(double *f, const uint16_t *cell, const double *in,
                                        int i, int nx, int ny, int pitch, size_t plane,
                                        hipStream_t s);
-// Single-precision specialisations, defined in lbm_kernels.hip.
-template <>
-hipError_t launch_sweep<float>(const SweepArgs<float> &a, bool check, hipStream_t s);
-template <>
-hipError_t launch_tb<float>(const SweepArgs<float> &a, const int32_t *tiles, int n_tiles,
-                            int steps, bool check, hipStream_t s);
-template <>
-hipError_t launch_rest_cells<float>(float *f, size_t plane, const int32_t *cells,
-                                    int count, int nx, int pitch, hipStream_t s);
-template <>
-hipError_t launch_rest_all<float>(float *f, size_t plane, hipStream_t s);
+// Single- and half-precision storage specialisations, defined in
+// lbm_kernels.hip.
+#define LBM_DECLARE_OFFSET(T)                                                             \
+    template <>                                                                            \
+    hipError_t launch_sweep<T>(const SweepArgs<T> &a, bool check, hipStream_t s);          \
+    template <>                                                                            \
+    hipError_t launch_tb<T>(const SweepArgs<T> &a, const int32_t *tiles, int n_tiles,      \
+                            int steps, bool check, hipStream_t s);                         \
+    template <>                                                                            \
+    hipError_t launch_rest_cells<T>(T * f, size_t plane, const int32_t *cells, int count,  \
+                                    int nx, int pitch, hipStream_t s);                     \
+    template <>                                                                            \
+    hipError_t launch_rest_all<T>(T * f, size_t plane, hipStream_t s);
+LBM_DECLARE_OFFSET(float)
+LBM_DECLARE_OFFSET(h16)
+LBM_DECLARE_OFFSET(bf16)
 
 }  // namespace lbm

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
+
 #include "lbm_internal.h"
 #include "lbm_sweep.h"
 
@@ -83,24 +85,36 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid,
 #define LBM_F32_POLY LBM_F32_COMPUTE
 #endif
 
-// One cell of one time step on single-precision offsets d_i = f_i - w_i,
-// arithmetic in CT (double by default: with float storage the rounding of
-// the arithmetic, not of the stored offsets, dominates the error of steady
-// fields).  Zou-He closure on inlet (velocity u_in, unknowns 1, 5, 8) and
-// outlet cells (density rho_out, zero transverse velocity, unknowns 3, 6, 7),
-// moments (Eq. 2), BGK relaxation (Eq. 1) to the equilibrium of Sec. 2.1
-// written for offsets: feq_i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2
-// - 1.5 u.u)).  Every sum pairs the populations that a reflection y -> -y
-// exchanges (2<->4, 5<->8, 6<->7) and every product maps to itself or its
-// exact negative under it, so on a mirror-symmetric lattice the computed
-// flow is mirror-symmetric bit for bit.  Multiply-adds are fused only inside
-// one expression, as written, so every kernel that inlines this function
-// rounds identically.
-struct F32Cell {
-    using T = float;
-    using CT = LBM_F32_COMPUTE;
+// One cell of one time step on offsets d_i = f_i - w_i stored as T (float,
+// or 16-bit for the reduced-storage forms), arithmetic in CT, velocity
+// polynomials in PT.  With float storage CT = PT = double: the rounding of
+// float arithmetic, not that of the stored offsets, would dominate the error
+// of steady fields.  The 16-bit forms relax in float, their storage rounding
+// being far larger than float arithmetic's.  Zou-He closure on inlet
+// (velocity u_in, unknowns 1, 5, 8) and outlet cells (density rho_out, zero
+// transverse velocity, unknowns 3, 6, 7), moments (Eq. 2), BGK relaxation
+// (Eq. 1) to the equilibrium of Sec. 2.1 written for offsets:
+// feq_i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u)).  Every sum
+// pairs the populations that a reflection y -> -y exchanges (2<->4, 5<->8,
+// 6<->7) and every product maps to itself or its exact negative under it, so
+// on a mirror-symmetric lattice the computed flow is mirror-symmetric bit for
+// bit.  Multiply-adds are fused only inside one expression, as written, so
+// every kernel that inlines this function rounds identically.
+template <typename Storage, typename Arith, typename Poly>
+struct OffsetCell {
+    using T = Storage;
+    using CT = Arith;
+    using PT = Poly;
+    __device__ static __forceinline__ CT load(T v) { return (CT)Sto<T>::to_d(v); }
+    __device__ static __forceinline__ CT load_f(T v) { return (CT)Sto<T>::to_f(v); }
+    __device__ static __forceinline__ T store(CT v) {
+        if constexpr (sizeof(CT) == 8)
+            return Sto<T>::from_d((double)v);
+        else
+            return Sto<T>::from_f((float)v);
+    }
     __device__ static __forceinline__ void update(CT (&d)[9], uint32_t type, CT uin,
-                                                  const SweepArgs<float> &a, double &mass,
+                                                  const SweepArgs<T> &a, double &mass,
                                                   double &ux_out, double &uy_out) {
 #pragma clang fp contract(on)
         if (type == kInlet) {
@@ -130,10 +144,6 @@ struct F32Cell {
         // Opposite directions i, opp(i) have c.u = +-cu: their equilibrium
         // offsets share the even part A = 4.5 cu^2 - 1.5 u.u and differ in the
         // sign of the odd part B = 3 cu.
-        // The velocity polynomials (magnitude ~0.1) are formed in PT; their
-        // rounding enters the offsets multiplied by w_i rho and stays well
-        // below the float storage rounding of the offsets themselves.
-        using PT = LBM_F32_POLY;
         const PT pux = (PT)ux, puy = (PT)uy;
         const PT puu15 = PT(1.5) * (pux * pux + puy * puy);
         auto relax_pair = [&](int i, int j, PT cu, CT w) {
@@ -155,6 +165,10 @@ struct F32Cell {
         uy_out = (double)uy;
     }
 };
+
+using F32Cell = OffsetCell<float, LBM_F32_COMPUTE, LBM_F32_POLY>;
+using H16Cell = OffsetCell<h16, float, float>;
+using BF16Cell = OffsetCell<bf16, float, float>;
 
 // Sum `count` groups of NV doubles in a fixed order (one block of 256).
 template <int NV>
@@ -190,7 +204,7 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroArgs<T> a) {
     if (!solid) {
         double d[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = (double)a.f[(size_t)i * a.plane + n];
+        for (int i = 0; i < 9; ++i) d[i] = Sto<T>::to_d(a.f[(size_t)i * a.plane + n]);
         double dr, jx, jy;
         moments_sym(d, dr, jx, jy);
         rho = 1.0 + dr;
@@ -203,8 +217,8 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroArgs<T> a) {
         a.uy[l] = uy;
     }
     if (a.uprev) {
-        a.uprev[n] = (T)ux;
-        a.uprev[a.plane + n] = (T)uy;
+        a.uprev[n] = ux;
+        a.uprev[a.plane + n] = uy;
     }
 }
 
@@ -220,7 +234,7 @@ __global__ __launch_bounds__(256) void mass_kernel(MacroArgs<T> a,
         if ((a.cell[n] >> 8) != kSolid) {
             double d[9], dr, jx, jy;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) d[i] = (double)a.f[(size_t)i * a.plane + n];
+            for (int i = 0; i < 9; ++i) d[i] = Sto<T>::to_d(a.f[(size_t)i * a.plane + n]);
             moments_sym(d, dr, jx, jy);
             v[0] = 1.0 + dr;
         }
@@ -244,7 +258,7 @@ __global__ void boundary_kernel(MacroArgs<T> a, const int32_t *out_y0,
     auto moments = [&](size_t n, double &rho, double &jx) {
         double d[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = (double)a.f[(size_t)i * a.plane + n];
+        for (int i = 0; i < 9; ++i) d[i] = Sto<T>::to_d(a.f[(size_t)i * a.plane + n]);
         double dr, jy;
         moments_sym(d, dr, jx, jy);
         rho = 1.0 + dr;
@@ -321,7 +335,7 @@ __global__ void zero_cells_kernel(T *f, size_t plane, const int32_t *cells,
     const int l = cells[k];
     const size_t n = (size_t)(l / nx) * pitch + (l % nx);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[(size_t)i * plane + n] = T(0);
+    for (int i = 0; i < 9; ++i) f[(size_t)i * plane + n] = Sto<T>::from_d(0.0);
 }
 
 template <typename T>
@@ -343,7 +357,7 @@ __global__ __launch_bounds__(256) void export_plane_kernel(
     const size_t n = (size_t)y * pitch + x;
     const bool solid = (cell[n] >> 8) == kSolid;
     out[(size_t)y * nx + x] =
-        solid ? 0.0 : wgt<double>(i) + (double)f[(size_t)i * plane + n];
+        solid ? 0.0 : wgt<double>(i) + Sto<T>::to_d(f[(size_t)i * plane + n]);
 }
 
 template <typename T>
@@ -356,7 +370,7 @@ __global__ __launch_bounds__(256) void import_plane_kernel(
     const size_t n = (size_t)y * pitch + x;
     const bool solid = (cell[n] >> 8) == kSolid;
     f[(size_t)i * plane + n] =
-        solid ? T(0) : (T)(in[(size_t)y * nx + x] - wgt<double>(i));
+        Sto<T>::from_d(solid ? 0.0 : in[(size_t)y * nx + x] - wgt<double>(i));
 }
 
 // ---------------------------------------------------------------------------
@@ -524,18 +538,21 @@ static inline dim3 grid_cells(int ncols, int ny) {
     return dim3((unsigned)((ncols + 63) / 64), (unsigned)((ny + 3) / 4));
 }
 
-template <>
-hipError_t launch_sweep<float>(const SweepArgs<float> &a, bool check, hipStream_t s) {
-    return sweep::launch_step<F32Cell>(a, check, s);
-}
-
-template <>
-hipError_t launch_tb<float>(const SweepArgs<float> &a, const int32_t *tiles, int n_tiles,
-                            int steps, bool check, hipStream_t s) {
-    return sweep::launch_tb<F32Cell, TbShape<float>::rows, TbShape<float>::halo,
-                             TbShape<float>::threads, true>(a, tiles, n_tiles, steps,
-                                                                   check, s);
-}
+#define LBM_OFFSET_LAUNCHERS(T, CELL)                                                  \
+    template <>                                                                          \
+    hipError_t launch_sweep<T>(const SweepArgs<T> &a, bool check, hipStream_t s) {       \
+        return sweep::launch_step<CELL>(a, check, s);                                    \
+    }                                                                                    \
+    template <>                                                                          \
+    hipError_t launch_tb<T>(const SweepArgs<T> &a, const int32_t *tiles, int n_tiles,    \
+                            int steps, bool check, hipStream_t s) {                      \
+        return sweep::launch_tb<CELL, TbShape<T>::rows, TbShape<T>::halo,                \
+                                TbShape<T>::threads, true>(a, tiles, n_tiles, steps,     \
+                                                           check, s);                    \
+    }
+LBM_OFFSET_LAUNCHERS(float, F32Cell)
+LBM_OFFSET_LAUNCHERS(h16, H16Cell)
+LBM_OFFSET_LAUNCHERS(bf16, BF16Cell)
 
 int64_t sweep_blocks(int nx, int ny) {
     const dim3 g = grid_cells(nx, ny);
@@ -587,24 +604,39 @@ hipError_t launch_build_cells(const uint8_t *types, uint16_t *cell, int nx,
     return hipGetLastError();
 }
 
-template <>
-hipError_t launch_rest_cells<float>(float *f, size_t plane, const int32_t *cells,
-                                    int count, int nx, int pitch, hipStream_t s) {
+template <typename T>
+hipError_t rest_cells_impl(T *f, size_t plane, const int32_t *cells, int count, int nx,
+                           int pitch, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(zero_cells_kernel<float>, dim3((count + 255) / 256),
-                       dim3(256), 0, s, f, plane, cells, count, nx, pitch);
+    hipLaunchKernelGGL(zero_cells_kernel<T>, dim3((count + 255) / 256), dim3(256), 0, s, f,
+                       plane, cells, count, nx, pitch);
     return hipGetLastError();
 }
 
-template <>
-hipError_t launch_rest_all<float>(float *f, size_t plane, hipStream_t s) {
+template <typename T>
+hipError_t rest_all_impl(T *f, size_t plane, hipStream_t s) {
     const size_t count = 9 * plane;
     size_t blocks = (count + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(fill_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       f, count, 0.0f);
+    T zero;
+    std::memset(&zero, 0, sizeof zero);  // +0 in every storage format
+    hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, f, count, zero);
     return hipGetLastError();
 }
+
+#define LBM_OFFSET_REST(T)                                                             \
+    template <>                                                                        \
+    hipError_t launch_rest_cells<T>(T * f, size_t plane, const int32_t *cells,         \
+                                    int count, int nx, int pitch, hipStream_t s) {     \
+        return rest_cells_impl<T>(f, plane, cells, count, nx, pitch, s);               \
+    }                                                                                  \
+    template <>                                                                        \
+    hipError_t launch_rest_all<T>(T * f, size_t plane, hipStream_t s) {                \
+        return rest_all_impl<T>(f, plane, s);                                          \
+    }
+LBM_OFFSET_REST(float)
+LBM_OFFSET_REST(h16)
+LBM_OFFSET_REST(bf16)
 
 template <typename T>
 hipError_t launch_export_plane(const T *f, const uint16_t *cell, double *out,
@@ -660,14 +692,18 @@ hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
     return hipGetLastError();
 }
 
-// Single-precision instantiations (double precision: lbm_f64.hip).
-template hipError_t launch_macro<float>(const MacroArgs<float> &, hipStream_t);
-template hipError_t launch_mass<float>(const MacroArgs<float> &, double *, hipStream_t);
-template hipError_t launch_boundary<float>(const MacroArgs<float> &, const int32_t *,
-                                           const int32_t *, int, double *, hipStream_t);
-template hipError_t launch_export_plane<float>(const float *, const uint16_t *, double *,
-                                               int, int, int, int, size_t, hipStream_t);
-template hipError_t launch_import_plane<float>(float *, const uint16_t *, const double *,
-                                               int, int, int, int, size_t, hipStream_t);
+// Offset-storage instantiations (double precision: lbm_f64.hip).
+#define LBM_OFFSET_INST(T)                                                                  \
+    template hipError_t launch_macro<T>(const MacroArgs<T> &, hipStream_t);                  \
+    template hipError_t launch_mass<T>(const MacroArgs<T> &, double *, hipStream_t);         \
+    template hipError_t launch_boundary<T>(const MacroArgs<T> &, const int32_t *,            \
+                                           const int32_t *, int, double *, hipStream_t);     \
+    template hipError_t launch_export_plane<T>(const T *, const uint16_t *, double *, int,   \
+                                               int, int, int, size_t, hipStream_t);          \
+    template hipError_t launch_import_plane<T>(T *, const uint16_t *, const double *, int,   \
+                                               int, int, int, size_t, hipStream_t);
+LBM_OFFSET_INST(float)
+LBM_OFFSET_INST(h16)
+LBM_OFFSET_INST(bf16)
 
 }  // namespace lbm

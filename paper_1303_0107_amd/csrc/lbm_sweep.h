@@ -1,6 +1,8 @@
 // The D2Q9 time-step kernels, generic in the per-cell arithmetic.
 //
-// A `Cell` policy supplies the storage type T and the update of one cell:
+// A `Cell` policy supplies the storage type T, the arithmetic type CT, the
+// conversions Cell::load (T -> CT) and Cell::store (CT -> T), and the update
+// of one cell:
 //     Cell::update(CT (&f)[9], type, uin, args, mass, ux, uy)
 // turns the nine pulled populations (after streaming, before the boundary
 // closure) into the post-collision populations, and reports the cell's
@@ -68,14 +70,14 @@ template <typename T>
 __device__ __forceinline__ void check_terms(const SweepArgs<T> &a, size_t n,
                                             double mass, double ux, double uy,
                                             double (&part)[4]) {
-    const double px = (double)a.uprev[n], py = (double)a.uprev[a.plane + n];
+    const double px = a.uprev[n], py = a.uprev[a.plane + n];
     const double dx = ux - px, dy = uy - py;
     part[0] += dx * dx + dy * dy;
     part[1] += ux * ux + uy * uy;
     part[2] += mass;
     part[3] += (isfinite(mass) && isfinite(ux) && isfinite(uy)) ? 0.0 : 1.0;
-    a.uprev[n] = (T)ux;
-    a.uprev[a.plane + n] = (T)uy;
+    a.uprev[n] = ux;
+    a.uprev[a.plane + n] = uy;
 }
 
 template <class Cell, bool CHECK>
@@ -97,12 +99,12 @@ __global__ __launch_bounds__(256) void step_kernel(SweepArgs<typename Cell::T> a
             const bool wall = i > 0 && ((cw >> (i - 1)) & 1u);
             const size_t src = wall ? (size_t)kOpp[i] * P + n
                                     : (size_t)i * P + n - kCx[i] - (ptrdiff_t)kCy[i] * a.pitch;
-            f[i] = (CT)a.fin[src];
+            f[i] = Cell::load(a.fin[src]);
         }
         double mass, ux, uy;
         Cell::update(f, type, type == kInlet ? (CT)a.uin[y] : CT(0), a, mass, ux, uy);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) a.fout[(size_t)i * P + n] = (T)f[i];
+        for (int i = 0; i < 9; ++i) a.fout[(size_t)i * P + n] = Cell::store(f[i]);
         if (CHECK) check_terms(a, n, mass, ux, uy, part);
     }
     if (CHECK) {
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
         const bool live = in && (cw[c] >> 8) != kSolid;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            L[i * PL + ry * RW + lane] = live ? a.fin[(size_t)i * a.plane + n] : T(0);
+            L[i * PL + ry * RW + lane] = live ? a.fin[(size_t)i * a.plane + n] : Cell::store(CT(0));
     }
     __syncthreads();
 
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
                     const bool wall = i > 0 && ((cw[c] >> (i - 1)) & 1u);
                     const int src = wall ? kOpp[i] * PL + ry * RW + lane
                                          : i * PL + (ry - kCy[i]) * RW + lane - kCx[i];
-                    f[i] = (CT)Ls[src];
+                    f[i] = Cell::load(Ls[src]);
                 }
                 double mass, ux, uy;
                 const int gy = oy + ry;
@@ -184,14 +186,14 @@ __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
                 if (last) {
                     const size_t n = (size_t)gy * a.pitch + gx;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) a.fout[(size_t)i * a.plane + n] = (T)f[i];
+                    for (int i = 0; i < 9; ++i) a.fout[(size_t)i * a.plane + n] = Cell::store(f[i]);
                     if (CHECK) check_terms(a, n, mass, ux, uy, part);
                 } else if (PP) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) Ld[i * PL + ry * RW + lane] = (T)f[i];
+                    for (int i = 0; i < 9; ++i) Ld[i * PL + ry * RW + lane] = Cell::store(f[i]);
                 } else {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) out[PP ? 0 : c][i] = (T)f[i];
+                    for (int i = 0; i < 9; ++i) out[PP ? 0 : c][i] = Cell::store(f[i]);
                 }
             }
         }

@@ -22,7 +22,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "lbm.h")
 LBM_OK, LBM_NOT_CONVERGED = 0, 1
 LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE = -1, -2, -3, -4
 LBM_SOLID, LBM_FLUID, LBM_INLET, LBM_OUTLET = 0, 1, 2, 3
-LBM_F64, LBM_F32 = 0, 1
+LBM_F64, LBM_F32, LBM_F32_S_F16, LBM_F32_S_BF16 = 0, 1, 2, 3
 LBM_WARM, LBM_COLD = 0, 1
 LBM_CRIT_PAPER, LBM_CRIT_SPEED = 0, 1
 
