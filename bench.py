@@ -40,6 +40,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC_PER_STEP = {
     ("distributor-1024x512-L3", "f32", "tb_kernel"): 14.902e6 / 8,
 }
+# The same for the batched kernel, per launch, keyed by (workload, storage,
+# shape, order).
+MEASURED_TRAFFIC_PER_LAUNCH = {}
 
 
 def workloads():
@@ -84,6 +87,120 @@ def cpu_baseline(types, w, seconds: float):
                       f"({dt:.1f} s), residual checks every 100 steps"}
 
 
+BATCH_WORKLOAD = "batch-256-candidates"
+
+
+def bench_batch(args) -> int:
+    """Batched candidates: 256 uneven distributors advanced together.  One
+    benchmark step = every candidate advanced by --batch-steps time steps
+    (one batch run).  value = all cells of all candidates times steps over
+    the wall time of the timed runs.  roofline: the batch kernel, algorithmic
+    bytes per launch = steps per launch * sum over candidates of
+    (18 s N_nonsolid + N), over the mean launch time (HIP events around each
+    run's launches on the batch's stream, divided by its launch count)."""
+    import numpy as np
+    import torch
+
+    from paper_1303_0107_amd import inputs as I
+    from paper_1303_0107_amd import lbm
+
+    prec = {"f64": lbm.LBM_F64, "f32": lbm.LBM_F32, "f16": lbm.LBM_F32_S_F16,
+            "bf16": lbm.LBM_F32_S_BF16}[args.precision]
+    s_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[args.precision]
+    arith = "f64" if args.precision in ("f64", "f32") else "f32"
+    cands = I.batch_candidates(count=args.batch_count, seed=4)
+    types = [c.types() for c in cands]
+    N = sum(t.size for t in types)
+    nns = sum(int(np.count_nonzero(t)) for t in types)
+    print(f"# {BATCH_WORKLOAD}: {len(cands)} lattices, {N} cells, {nns} non-solid, "
+          f"precision {args.precision}", file=sys.stderr, flush=True)
+    copy_gbs = copy_ceiling()
+    lats = [lbm.Lattice(t, c.tau, c.u_peak, precision=prec) for t, c in zip(types, cands)]
+    bt = lbm.Batch(lats)
+    t0 = time.perf_counter()
+    bv, bo, trial = bt.tune(args.tune_steps)
+    print(f"# tuned in {time.perf_counter() - t0:.1f} s: shape {bv} order {bo}; ms/step "
+          + " ".join(f"{x:.3f}" for x in trial), file=sys.stderr, flush=True)
+    if bv < lbm.lbm_tb_variant_count(prec):
+        rows, halo, tw, th = lbm.lbm_tb_variant_info(prec, bv)
+        shape = {"kind": "temporal blocking", "rows": rows, "halo": halo, "tile": [tw, th],
+                 "order": bo}
+        kname = "tb_batch_kernel"
+    else:
+        shape = {"kind": "one step per launch", "block": [64, 4], "order": bo}
+        kname = "step_batch_kernel"
+    for _ in range(args.warmup):
+        bt.run(args.batch_steps)
+    torch.cuda.synchronize()
+    launch_ms = 0.0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ms = bt.run(args.batch_steps)
+        launch_ms += ms
+        print(f"# step {i}: {args.batch_steps} steps in {ms:.1f} ms", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    items, spl, _ = bt.info()
+    launches_per_run = -(-args.batch_steps // spl)
+    launches = launches_per_run * args.steps
+    total_steps = args.batch_steps * args.steps
+    mlups = N * total_steps / wall / 1e6
+    bytes_per_step = 18 * s_bytes * nns + N
+    avg_ms = launch_ms / launches
+    bytes_per_launch = bytes_per_step * args.batch_steps / launches_per_run
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    flows = []
+    for lat in lats[:4]:
+        flow, st = lat.stats()
+        flows.append(round(float(st.dp), 9))
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": arith,
+        "data": "synthetic",
+        "config": {
+            "workload": BATCH_WORKLOAD, "lattices": len(cands), "cells": N,
+            "non_solid_cells": nns, "storage": args.precision, "arithmetic": arith,
+            "step": f"every lattice advanced {args.batch_steps} time steps in one batch",
+            "sizes": "nx 128..1024, ny 64..512 (multiples of 64), 2-4 levels, "
+                     "tau U[0.55,1], u_peak U[0.02,0.06]",
+            "mflups": round(nns * total_steps / wall / 1e6, 2),
+            "tuned_shape": shape,
+            "tune_ms_per_step": [round(x, 4) for x in trial],
+            "dp_first_members": flows,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": MEASURED_TRAFFIC_PER_LAUNCH.get((BATCH_WORKLOAD, args.precision, bv, bo)),
+            "kernel": f"{kname} ({args.precision} storage)",
+            "bytes_per_step": bytes_per_step, "steps_per_launch": spl,
+            "bytes_per_launch": round(bytes_per_launch), "launches": launches,
+            "work_items_per_launch": items,
+            "avg_launch_us": round(avg_ms * 1e3, 3),
+            "copy_ceiling_GBs": round(copy_gbs, 1),
+            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
+        },
+    }
+    if not args.no_cpu:
+        big = max(range(len(cands)), key=lambda i: types[i].size)
+        out["cpu_baseline"] = cpu_baseline(types[big], cands[big], args.cpu_seconds)
+    bt.close()
+    for lat in lats:
+        lat.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +216,11 @@ def main() -> int:
                     help="step cap of the untimed solve from rest (default: workload's)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=10000,
+                    help="time steps per benchmark step of the batched workload")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--tune-steps", type=int, default=256,
+                    help="steps per autotuner trial (batched workload)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -115,6 +237,8 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     torch.cuda.set_device(0)
+    if args.workload == BATCH_WORKLOAD:
+        return bench_batch(args)
     w = workloads()[args.workload]
     types = w.types()
     N = types.size

@@ -238,6 +238,107 @@ int lbm_bench_sweep(lbm_handle *h, int32_t steps, double *ms_per_step);
 int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *steps,
                        int64_t *launches, double *total_ms);
 
+/*
+ * Region shapes of the temporally blocked sweep.  A launch loads a region of
+ * 64 x rows cells into LDS and advances its inner tile of (64 - 2 halo) x
+ * (rows - 2 halo) cells by up to `halo` time steps of Sec. 2.1 (the ring of
+ * width halo around the tile is recomputed by its neighbours).  The shape
+ * changes only the speed: every shape gives the same bits as one sweep per
+ * step.
+ *
+ * lbm_tb_variant_count: number of shapes compiled for a precision (0 for an
+ * unknown precision).  lbm_tb_variant_info: shape `variant` of `precision`;
+ * any output pointer may be NULL.  Errors: LBM_EINVAL.
+ */
+int32_t lbm_tb_variant_count(int32_t precision);
+int lbm_tb_variant_info(int32_t precision, int32_t variant, int32_t *rows,
+                        int32_t *halo, int32_t *tile_w, int32_t *tile_h);
+
+/* Use region shape `variant` for the handle's sweeps from now on.
+ * Errors: LBM_EINVAL (NULL handle, variant out of range), LBM_EHIP. */
+int lbm_set_tb_variant(lbm_handle *h, int32_t variant);
+
+/*
+ * Autotuner: time every compiled shape on `trial_steps` (>= 1) real time
+ * steps of this lattice, keep the fastest, and leave the state, the step
+ * counter and the residual exactly as they were (both population buffers
+ * are saved and restored, so the call needs their size again in scratch
+ * memory while it runs).
+ *   best  receives the chosen shape (may be NULL).
+ *   ms    receives the mean time per step of each shape (ms_cap entries;
+ *         may be NULL when ms_cap is 0).
+ * Errors: LBM_EINVAL (NULL handle, trial_steps < 1, ms_cap below the shape
+ * count while ms is not NULL), LBM_ENOMEM, LBM_EHIP.
+ */
+int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *best,
+                 double *ms, int32_t ms_cap);
+
+/*
+ * Batched sweeps: many lattices of one precision, each of its own size,
+ * geometry, tau, inlet peak and outlet density, advanced together.  Every
+ * launch covers all tiles holding a non-solid cell of all member lattices, so
+ * small lattices share the chip instead of each leaving most of it idle; each
+ * lattice computes exactly what lbm_run_to_steady computes for it alone (the
+ * LBM of Sec. 2.1 with the boundaries of Sec. 3.3), bit for bit.  The time
+ * loop is replayed from a captured HIP graph.
+ *
+ * lbm_batch_create: handles[0..count-1] (count >= 1) must be distinct, of one
+ * precision and on the current device; they stay owned by the caller and
+ * must outlive the batch.  hip_stream: the stream the batch launches on
+ * (borrowed; NULL: the null stream).  The batch starts with shape 0 and
+ * work-list order 0.  Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EHIP.
+ */
+typedef struct lbm_batch lbm_batch;
+int lbm_batch_create(lbm_handle *const *handles, int32_t count,
+                     void *hip_stream, lbm_batch **out);
+
+/*
+ * Advance every member lattice by `steps` (>= 0) time steps without residual
+ * checks.  Waits for the members' own streams first and for the batch's
+ * stream before returning.  Members whose mask changed since the last call
+ * (lbm_shape_update) are picked up automatically.  Each member's step
+ * counter advances by `steps`; its residual becomes NaN (unknown) until its
+ * next lbm_run_to_steady.
+ *   elapsed_ms  receives the time between HIP events recorded on the
+ *               batch's stream around the sweep launches (may be NULL).
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EHIP.
+ */
+int lbm_batch_run(lbm_batch *b, int64_t steps, double *elapsed_ms);
+
+/*
+ * Choose the batch's configuration.  variant in [0, lbm_tb_variant_count)
+ * selects a region shape of the temporally blocked sweep (as for
+ * lbm_set_tb_variant); variant = lbm_tb_variant_count selects one time step
+ * per launch over the 64 x 4 cell blocks that hold a non-solid cell.  Work
+ * list `order`: 0 = lattice by lattice, tiles row by row; 1 = the same list
+ * dealt so that consecutive tiles run on the same accelerator complex (XCD)
+ * of the chip, which shares their halo rows in that XCD's L2 cache.  Neither
+ * changes the results.  Errors: LBM_EINVAL.
+ */
+int lbm_batch_configure(lbm_batch *b, int32_t variant, int32_t order);
+
+/*
+ * Autotuner for a batch: time every (variant, order) pair of
+ * lbm_batch_configure on `trial_steps` real steps of all members, keep the
+ * fastest and restore every member's state, step counter and residual
+ * exactly (scratch memory of twice the members' population buffers while it
+ * runs).  Configuration c = 2 * variant + order; ms receives the mean time
+ * per step of each (ms_cap >= 2 x (shape count + 1), or ms NULL);
+ * best_variant, best_order may be NULL.
+ * Errors: LBM_EINVAL, LBM_ENOMEM, LBM_EHIP.
+ */
+int lbm_batch_tune(lbm_batch *b, int32_t trial_steps, int32_t *best_variant,
+                   int32_t *best_order, double *ms, int32_t ms_cap);
+
+/* Work items (tiles or blocks) per launch, time steps per launch (the halo
+ * of the shape, or 1) and the summed non-solid cell count of the members,
+ * for throughput accounting; any pointer may be NULL. */
+int lbm_batch_info(lbm_batch *b, int64_t *items, int32_t *steps_per_launch,
+                   int64_t *nonsolid_cells);
+
+/* Release a batch (the member handles are untouched; NULL is ignored). */
+void lbm_batch_destroy(lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -256,6 +256,8 @@ struct lbm_handle {
     DeviceBuffer tiles;
     std::vector<int32_t> tile_host;
     int n_tiles = 0;
+    int tb_variant = 0;         // region shape (index into the compiled shapes)
+    uint64_t mask_version = 0;  // bumped whenever the tile list is rebuilt
     int64_t prof_kernels = 0;
 
     size_t N() const { return (size_t)nx * ny; }
@@ -275,18 +277,49 @@ struct lbm_handle {
 
 namespace {
 
-int tile_width(int precision) {
-    return with_storage(precision, [](auto t) { return tile_w<decltype(t)>(); });
+int tb_variant_count(int precision) {
+    return with_storage(precision, [](auto t) { return TbVariants<decltype(t)>::count; });
 }
-int tile_height(int precision) {
-    return with_storage(precision, [](auto t) { return tile_h<decltype(t)>(); });
+TbVariant tb_shape(int precision, int variant) {
+    return with_storage(precision, [&](auto t) { return TbVariants<decltype(t)>::v[variant]; });
 }
-int steps_per_launch(int precision) {
-    return with_storage(precision, [](auto t) { return TbShape<decltype(t)>::halo; });
+int tile_width(int precision, int variant) { return 64 - 2 * tb_shape(precision, variant).halo; }
+int tile_height(int precision, int variant) {
+    const TbVariant v = tb_shape(precision, variant);
+    return v.rows - 2 * v.halo;
 }
-size_t tile_count(int nx, int ny, int precision) {
-    const int w = tile_width(precision), hh = tile_height(precision);
+int steps_per_launch(int precision, int variant) { return tb_shape(precision, variant).halo; }
+size_t tile_count(int nx, int ny, int precision, int variant) {
+    const int w = tile_width(precision, variant), hh = tile_height(precision, variant);
     return (size_t)((nx + w - 1) / w) * ((ny + hh - 1) / hh);
+}
+// The largest tile count over the compiled shapes (sizes the tile list and
+// the per-tile partials once for any shape).
+size_t max_tile_count(int nx, int ny, int precision) {
+    size_t m = 0;
+    for (int v = 0; v < tb_variant_count(precision); ++v)
+        m = std::max(m, tile_count(nx, ny, precision, v));
+    return m;
+}
+
+// Tiles of a tw x th tiling whose cells include a non-solid one, packed as
+// (tile row << 16 | tile column).
+std::vector<int32_t> active_tiles(const std::vector<uint8_t> &types, int nx, int ny, int tw,
+                                  int th) {
+    const int ntx = (nx + tw - 1) / tw, nty = (ny + th - 1) / th;
+    std::vector<int32_t> out;
+    for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) {
+            bool any = false;
+            for (int y = ty * th; y < std::min(ny, (ty + 1) * th) && !any; ++y)
+                for (int x = tx * tw; x < std::min(nx, (tx + 1) * tw); ++x)
+                    if (types[(size_t)y * nx + x] != LBM_SOLID) {
+                        any = true;
+                        break;
+                    }
+            if (any) out.push_back((ty << 16) | tx);
+        }
+    return out;
 }
 
 size_t footprint(int nx, int ny, int precision) {
@@ -298,7 +331,7 @@ size_t footprint(int nx, int ny, int precision) {
     b += N;                                  // type map
     b += (size_t)ny * sizeof(double);        // inlet profile
     b += 2 * plane * sizeof(double);         // u_prev
-    const size_t ntiles = tile_count(nx, ny, precision);
+    const size_t ntiles = max_tile_count(nx, ny, precision);
     b += std::max((size_t)sweep_blocks(nx, ny), ntiles) * 4 * sizeof(double);
     b += ntiles * sizeof(int32_t);
     b += 3 * N * sizeof(double);             // macro field (exchange step)
@@ -327,29 +360,19 @@ void compute_ports(lbm_handle *h) {
     }
 }
 
-// Tiles of the temporal-blocking sweep whose cells include a non-solid one,
-// packed as (tile row << 16 | tile column), uploaded to the device.
+// Tiles of the temporal-blocking sweep (current shape) whose cells include a
+// non-solid one, uploaded to the device.
 void rebuild_tiles(lbm_handle *h) {
-    const int kTileW = tile_width(h->precision), kTileH = tile_height(h->precision);
-    const int ntx = (h->nx + kTileW - 1) / kTileW, nty = (h->ny + kTileH - 1) / kTileH;
-    h->tile_host.clear();
-    for (int ty = 0; ty < nty; ++ty)
-        for (int tx = 0; tx < ntx; ++tx) {
-            bool any = false;
-            for (int y = ty * kTileH; y < std::min(h->ny, (ty + 1) * kTileH) && !any; ++y)
-                for (int x = tx * kTileW; x < std::min(h->nx, (tx + 1) * kTileW); ++x)
-                    if (h->host_types[(size_t)y * h->nx + x] != LBM_SOLID) {
-                        any = true;
-                        break;
-                    }
-            if (any) h->tile_host.push_back((ty << 16) | tx);
-        }
+    h->tile_host = active_tiles(h->host_types, h->nx, h->ny,
+                                tile_width(h->precision, h->tb_variant),
+                                tile_height(h->precision, h->tb_variant));
     h->n_tiles = (int)h->tile_host.size();
-    h->tiles.ensure((size_t)ntx * nty * sizeof(int32_t));
+    h->tiles.ensure(max_tile_count(h->nx, h->ny, h->precision) * sizeof(int32_t));
     if (h->n_tiles > 0)
         HIP_TRY(hipMemcpyAsync(h->tiles.p, h->tile_host.data(), h->n_tiles * sizeof(int32_t),
                                hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    ++h->mask_version;
 }
 
 // Parabolic inlet profile (Sec. 3.3) on each maximal run of inlet rows,
@@ -477,10 +500,11 @@ template <typename T>
 void advance(lbm_handle *h, int64_t n, bool check) {
     if (h->use_tb) {
         while (n > 0) {
-            const int s = (int)std::min<int64_t>(n, steps_per_launch(h->precision));
+            const int s =
+                (int)std::min<int64_t>(n, steps_per_launch(h->precision, h->tb_variant));
             n -= s;
             HIP_TRY(launch_tb<T>(sweep_args<T>(h, check && n == 0), h->tiles.as<int32_t>(),
-                                 h->n_tiles, s, check && n == 0, h->stream));
+                                 h->n_tiles, s, check && n == 0, h->tb_variant, h->stream));
             h->cur = 1 - h->cur;
             ++h->prof_kernels;
         }
@@ -642,6 +666,259 @@ int guard_hip(const HipFail &f) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Autotuning and batches.
+
+namespace {
+
+// Copies of both population buffers of a handle and its counters: tuning
+// trials run real steps and must leave no trace.
+struct Saved {
+    DeviceBuffer f[2];
+    int cur = 0;
+    int64_t steps = 0;
+    double residual = 0.0;
+};
+
+void save_state(lbm_handle *h, Saved &sv) {
+    const size_t bytes = 9 * h->plane * h->esize();
+    for (int b = 0; b < 2; ++b) {
+        sv.f[b].ensure(bytes);
+        HIP_TRY(hipMemcpyAsync(sv.f[b].p, h->f[b].p, bytes, hipMemcpyDeviceToDevice,
+                               h->stream));
+    }
+    sv.cur = h->cur;
+    sv.steps = h->steps;
+    sv.residual = h->last_residual;
+}
+
+void restore_state(lbm_handle *h, const Saved &sv) {
+    const size_t bytes = 9 * h->plane * h->esize();
+    for (int b = 0; b < 2; ++b)
+        HIP_TRY(hipMemcpyAsync(h->f[b].p, sv.f[b].p, bytes, hipMemcpyDeviceToDevice,
+                               h->stream));
+    h->cur = sv.cur;
+    h->steps = sv.steps;
+    h->last_residual = sv.residual;
+}
+
+struct EventPair {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    EventPair() {
+        for (hipEvent_t &x : e) HIP_TRY(hipEventCreate(&x));
+    }
+    ~EventPair() {
+        for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    double ms() const {
+        float v = 0.f;
+        HIP_TRY(hipEventElapsedTime(&v, e[0], e[1]));
+        return (double)v;
+    }
+};
+
+// Mean time per step of `n` steps after one untimed launch's worth.
+template <typename T>
+double time_handle_steps(lbm_handle *h, int64_t n) {
+    EventPair ev;
+    advance<T>(h, steps_per_launch(h->precision, h->tb_variant), false);
+    HIP_TRY(hipEventRecord(ev.e[0], h->stream));
+    advance<T>(h, n, false);
+    HIP_TRY(hipEventRecord(ev.e[1], h->stream));
+    HIP_TRY(hipEventSynchronize(ev.e[1]));
+    return ev.ms() / (double)n;
+}
+
+}  // namespace
+
+struct lbm_batch {
+    std::vector<lbm_handle *> hs;
+    std::vector<uint64_t> versions;
+    int precision = 0, device = 0, variant = 0, order = 0;
+    hipStream_t stream = nullptr;
+    DeviceBuffer args;       // SweepArgs of every member: parity 0, then parity 1
+    DeviceBuffer lat, tiles; // work list (lat < 0: padding item)
+    int64_t n_items = 0;     // launch grid
+    int64_t n_real = 0;      // real tiles
+    bool dirty = true;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    // Replayable runs of an even number of launches, starting at parity 0.
+    struct Graph {
+        int64_t launches;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t capture_stream = nullptr;
+    bool use_graphs = true;
+
+    void drop_graphs() {
+        for (Graph &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
+    ~lbm_batch() {
+        drop_graphs();
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+namespace {
+
+// Launches per captured graph (even, so that every replay starts at parity 0).
+constexpr int64_t kBatchGraphLaunches = 16;
+
+// Batch variants: 0..count-1 the region shapes of the temporally blocked
+// sweep, count = one time step per launch over 64 x 4 blocks.
+bool batch_single_step(const lbm_batch *b) {
+    return b->variant == tb_variant_count(b->precision);
+}
+int batch_steps_per_launch(const lbm_batch *b) {
+    return batch_single_step(b) ? 1 : steps_per_launch(b->precision, b->variant);
+}
+
+void build_work(lbm_batch *b) {
+    const bool one = batch_single_step(b);
+    const int tw = one ? 64 : tile_width(b->precision, b->variant);
+    const int th = one ? 4 : tile_height(b->precision, b->variant);
+    std::vector<int32_t> L, Tl;
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        const lbm_handle *h = b->hs[i];
+        for (int32_t t : active_tiles(h->host_types, h->nx, h->ny, tw, th)) {
+            L.push_back((int32_t)i);
+            Tl.push_back(t);
+        }
+        b->versions[i] = h->mask_version;
+    }
+    b->n_real = (int64_t)L.size();
+    if (b->order == 1 && !L.empty()) {
+        // Workgroup g runs on XCD g mod 8: deal contiguous runs of the list
+        // to the eight XCDs so that neighbouring tiles share an L2.
+        const int64_t per = (b->n_real + 7) / 8;
+        std::vector<int32_t> L2((size_t)per * 8, -1), T2((size_t)per * 8, 0);
+        for (int64_t k = 0; k < b->n_real; ++k) {
+            const int64_t slot = (k % per) * 8 + k / per;
+            L2[slot] = L[k];
+            T2[slot] = Tl[k];
+        }
+        L.swap(L2);
+        Tl.swap(T2);
+    }
+    b->n_items = (int64_t)L.size();
+    b->lat.ensure(std::max<size_t>(1, L.size()) * sizeof(int32_t));
+    b->tiles.ensure(std::max<size_t>(1, L.size()) * sizeof(int32_t));
+    if (!L.empty()) {
+        HIP_TRY(hipMemcpyAsync(b->lat.p, L.data(), L.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->tiles.p, Tl.data(), Tl.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, b->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->drop_graphs();
+    b->dirty = false;
+}
+
+bool work_stale(const lbm_batch *b) {
+    if (b->dirty) return true;
+    for (size_t i = 0; i < b->hs.size(); ++i)
+        if (b->versions[i] != b->hs[i]->mask_version) return true;
+    return false;
+}
+
+template <typename T>
+hipError_t batch_launch(lbm_batch *b, int parity, int steps, hipStream_t s) {
+    const SweepArgs<T> *A = b->args.as<SweepArgs<T>>() + (size_t)parity * b->hs.size();
+    if (batch_single_step(b))
+        return launch_step_batch<T>(A, b->lat.as<int32_t>(), b->tiles.as<int32_t>(),
+                                    (int)b->n_items, s);
+    return launch_tb_batch<T>(A, b->lat.as<int32_t>(), b->tiles.as<int32_t>(),
+                              (int)b->n_items, steps, b->variant, s);
+}
+
+template <typename T>
+hipGraphExec_t batch_graph(lbm_batch *b, int64_t launches) {
+    for (const auto &g : b->graphs)
+        if (g.launches == launches) return g.exec;
+    if (!b->capture_stream)
+        HIP_TRY(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+    const int H = batch_steps_per_launch(b);
+    // Kernel attributes are set outside the capture (an empty launch does it).
+    if (!batch_single_step(b))
+        HIP_TRY(launch_tb_batch<T>(nullptr, nullptr, nullptr, 0, H, b->variant, b->stream));
+    HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    for (int64_t k = 0; k < launches && err == hipSuccess; ++k)
+        err = batch_launch<T>(b, (int)(k % 2), H, b->capture_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t end = hipStreamEndCapture(b->capture_stream, &graph);
+    HIP_TRY(err);
+    HIP_TRY(end);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_TRY(inst);
+    b->graphs.push_back({launches, exec});
+    return exec;
+}
+
+template <typename T>
+double batch_run_impl(lbm_batch *b, int64_t steps) {
+    if (work_stale(b)) build_work(b);
+    // The members' own queued work comes first.
+    for (size_t i = 0; i < b->hs.size(); ++i) {
+        bool seen = false;
+        for (size_t j = 0; j < i && !seen; ++j) seen = b->hs[j]->stream == b->hs[i]->stream;
+        if (!seen) HIP_TRY(hipStreamSynchronize(b->hs[i]->stream));
+    }
+    const size_t n = b->hs.size();
+    const size_t bytes = 2 * n * sizeof(SweepArgs<T>);
+    if (b->pinned_bytes < bytes) {
+        if (b->pinned) (void)hipHostFree(b->pinned);
+        b->pinned = nullptr;
+        b->pinned_bytes = 0;
+        HIP_TRY(hipHostMalloc(&b->pinned, bytes, hipHostMallocDefault));
+        b->pinned_bytes = bytes;
+    }
+    SweepArgs<T> *pa = static_cast<SweepArgs<T> *>(b->pinned);
+    for (size_t i = 0; i < n; ++i) {
+        lbm_handle *h = b->hs[i];
+        pa[i] = sweep_args<T>(h, false);
+        pa[n + i] = pa[i];
+        pa[n + i].fin = pa[i].fout;
+        pa[n + i].fout = const_cast<T *>(pa[i].fin);
+    }
+    HIP_TRY(hipMemcpyAsync(b->args.p, pa, bytes, hipMemcpyHostToDevice, b->stream));
+
+    const int H = batch_steps_per_launch(b);
+    const int64_t full = steps / H;
+    const int rem = (int)(steps % H);
+    int64_t done = 0;
+    hipGraphExec_t exec = nullptr;
+    if (b->use_graphs && full >= kBatchGraphLaunches && b->n_items > 0)
+        exec = batch_graph<T>(b, kBatchGraphLaunches);
+    EventPair ev;
+    HIP_TRY(hipEventRecord(ev.e[0], b->stream));
+    if (exec)
+        for (; done + kBatchGraphLaunches <= full; done += kBatchGraphLaunches)
+            HIP_TRY(hipGraphLaunch(exec, b->stream));
+    for (; done < full; ++done) HIP_TRY(batch_launch<T>(b, (int)(done % 2), H, b->stream));
+    if (rem > 0) {
+        HIP_TRY(batch_launch<T>(b, (int)(done % 2), rem, b->stream));
+        ++done;
+    }
+    HIP_TRY(hipEventRecord(ev.e[1], b->stream));
+    HIP_TRY(hipEventSynchronize(ev.e[1]));
+    for (lbm_handle *h : b->hs) {
+        if (done % 2) h->cur = 1 - h->cur;
+        h->steps += steps;
+        if (steps > 0) h->last_residual = std::nan("");
+    }
+    return ev.ms();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 extern "C" {
 
 const char *lbm_last_error(void) { return g_error.c_str(); }
@@ -693,7 +970,7 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         h->types.ensure(h->N());
         h->uin.ensure((size_t)h->ny * sizeof(double));
         h->uprev.ensure(2 * h->plane * sizeof(double));
-        const size_t ntiles = tile_count(h->nx, h->ny, h->precision);
+        const size_t ntiles = max_tile_count(h->nx, h->ny, h->precision);
         h->partials.ensure(std::max((size_t)sweep_blocks(h->nx, h->ny), ntiles) * 4 *
                            sizeof(double));
         h->red.ensure(64 * sizeof(double));
@@ -1091,6 +1368,226 @@ int lbm_set_state(lbm_handle *h, const double *f, size_t n) {
         return fail(LBM_ENOMEM, "allocation failed");
     }
     return LBM_OK;
+}
+
+int32_t lbm_tb_variant_count(int32_t precision) {
+    if (precision < LBM_F64 || precision > LBM_F32_S_BF16) return 0;
+    return tb_variant_count(precision);
+}
+
+int lbm_tb_variant_info(int32_t precision, int32_t variant, int32_t *rows, int32_t *halo,
+                        int32_t *tile_w, int32_t *tile_h) {
+    g_error.clear();
+    if (variant < 0 || variant >= lbm_tb_variant_count(precision))
+        return fail(LBM_EINVAL, "unknown precision or shape");
+    const TbVariant v = tb_shape(precision, variant);
+    if (rows) *rows = v.rows;
+    if (halo) *halo = v.halo;
+    if (tile_w) *tile_w = tile_width(precision, variant);
+    if (tile_h) *tile_h = tile_height(precision, variant);
+    return LBM_OK;
+}
+
+int lbm_set_tb_variant(lbm_handle *h, int32_t variant) {
+    g_error.clear();
+    if (!h) return fail(LBM_EINVAL, "null handle");
+    if (variant < 0 || variant >= tb_variant_count(h->precision))
+        return fail(LBM_EINVAL, "shape out of range");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        h->tb_variant = variant;
+        rebuild_tiles(h);
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *best, double *ms,
+                 int32_t ms_cap) {
+    g_error.clear();
+    if (!h || trial_steps < 1) return fail(LBM_EINVAL, "null handle or trial_steps < 1");
+    const int nv = tb_variant_count(h->precision);
+    if (ms && ms_cap < nv) return fail(LBM_EINVAL, "ms_cap below the shape count");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        Saved sv;
+        save_state(h, sv);
+        int bv = h->tb_variant;
+        double bms = INFINITY;
+        for (int v = 0; v < nv; ++v) {
+            h->tb_variant = v;
+            rebuild_tiles(h);
+            const double t = with_storage(h->precision, [&](auto x) {
+                return time_handle_steps<decltype(x)>(h, trial_steps);
+            });
+            restore_state(h, sv);
+            if (ms) ms[v] = t;
+            if (t < bms) {
+                bms = t;
+                bv = v;
+            }
+        }
+        h->tb_variant = bv;
+        rebuild_tiles(h);
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (best) *best = bv;
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_create(lbm_handle *const *handles, int32_t count, void *hip_stream,
+                     lbm_batch **out) {
+    g_error.clear();
+    if (!out) return fail(LBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!handles || count < 1) return fail(LBM_EINVAL, "at least one handle required");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(LBM_EHIP, "no current device");
+    for (int32_t i = 0; i < count; ++i) {
+        if (!handles[i]) return fail(LBM_EINVAL, "null handle in the list");
+        if (handles[i]->precision != handles[0]->precision)
+            return fail(LBM_EINVAL, "handles of different precision");
+        if (handles[i]->device != dev)
+            return fail(LBM_EINVAL, "handle not on the current device");
+        for (int32_t j = 0; j < i; ++j)
+            if (handles[j] == handles[i]) return fail(LBM_EINVAL, "handle listed twice");
+    }
+    lbm_batch *b = new (std::nothrow) lbm_batch;
+    if (!b) return fail(LBM_ENOMEM, "host allocation failed");
+    try {
+        b->hs.assign(handles, handles + count);
+        b->versions.assign((size_t)count, 0);
+        b->precision = handles[0]->precision;
+        b->device = dev;
+        b->stream = static_cast<hipStream_t>(hip_stream);
+        const char *g = std::getenv("LBM_GRAPHS");
+        b->use_graphs = !(g && g[0] == '0');
+        const size_t args_bytes = with_storage(b->precision, [&](auto t) {
+            return 2 * (size_t)count * sizeof(SweepArgs<decltype(t)>);
+        });
+        b->args.ensure(args_bytes);
+        build_work(b);
+    } catch (const std::bad_alloc &) {
+        delete b;
+        return fail(LBM_ENOMEM, "device allocation failed");
+    } catch (const HipFail &e) {
+        delete b;
+        return guard_hip(e);
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_run(lbm_batch *b, int64_t steps, double *elapsed_ms) {
+    g_error.clear();
+    if (!b || steps < 0) return fail(LBM_EINVAL, "null batch or steps < 0");
+    try {
+        HIP_TRY(hipSetDevice(b->device));
+        const double ms = with_storage(b->precision, [&](auto t) {
+            return batch_run_impl<decltype(t)>(b, steps);
+        });
+        if (elapsed_ms) *elapsed_ms = ms;
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_configure(lbm_batch *b, int32_t variant, int32_t order) {
+    g_error.clear();
+    if (!b) return fail(LBM_EINVAL, "null batch");
+    if (variant < 0 || variant > tb_variant_count(b->precision) || order < 0 || order > 1)
+        return fail(LBM_EINVAL, "shape or order out of range");
+    if (variant != b->variant || order != b->order) {
+        b->variant = variant;
+        b->order = order;
+        b->dirty = true;
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_tune(lbm_batch *b, int32_t trial_steps, int32_t *best_variant,
+                   int32_t *best_order, double *ms, int32_t ms_cap) {
+    g_error.clear();
+    if (!b || trial_steps < 1) return fail(LBM_EINVAL, "null batch or trial_steps < 1");
+    const int nv = tb_variant_count(b->precision) + 1;  // shapes + single step
+    if (ms && ms_cap < 2 * nv) return fail(LBM_EINVAL, "ms_cap below 2 x (shape count + 1)");
+    try {
+        HIP_TRY(hipSetDevice(b->device));
+        std::vector<Saved> sv(b->hs.size());
+        for (size_t i = 0; i < b->hs.size(); ++i) save_state(b->hs[i], sv[i]);
+        for (lbm_handle *h : b->hs) HIP_TRY(hipStreamSynchronize(h->stream));
+        int bv = b->variant, bo = b->order;
+        double bms = INFINITY;
+        for (int v = 0; v < nv; ++v)
+            for (int o = 0; o < 2; ++o) {
+                b->variant = v;
+                b->order = o;
+                b->dirty = true;
+                const int H = batch_steps_per_launch(b);
+                const double t = with_storage(b->precision, [&](auto x) {
+                    batch_run_impl<decltype(x)>(b, H);  // untimed
+                    return batch_run_impl<decltype(x)>(b, trial_steps) / trial_steps;
+                });
+                for (size_t i = 0; i < b->hs.size(); ++i) restore_state(b->hs[i], sv[i]);
+                for (lbm_handle *h : b->hs) HIP_TRY(hipStreamSynchronize(h->stream));
+                if (ms) ms[2 * v + o] = t;
+                if (t < bms) {
+                    bms = t;
+                    bv = v;
+                    bo = o;
+                }
+            }
+        b->variant = bv;
+        b->order = bo;
+        b->dirty = true;
+        build_work(b);
+        if (best_variant) *best_variant = bv;
+        if (best_order) *best_order = bo;
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_info(lbm_batch *b, int64_t *items, int32_t *steps_per_launch_out,
+                   int64_t *nonsolid_cells) {
+    g_error.clear();
+    if (!b) return fail(LBM_EINVAL, "null batch");
+    try {
+        HIP_TRY(hipSetDevice(b->device));
+        if (work_stale(b)) build_work(b);
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    if (items) *items = b->n_real;
+    if (steps_per_launch_out) *steps_per_launch_out = batch_steps_per_launch(b);
+    if (nonsolid_cells) {
+        int64_t c = 0;
+        for (const lbm_handle *h : b->hs) c += h->n_nonsolid;
+        *nonsolid_cells = c;
+    }
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
 }
 
 }  // extern "C"

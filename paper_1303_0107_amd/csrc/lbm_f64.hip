@@ -244,10 +244,22 @@ hipError_t launch_sweep<double>(const SweepArgs<double> &a, bool check, hipStrea
 
 template <>
 hipError_t launch_tb<double>(const SweepArgs<double> &a, const int32_t *tiles, int n_tiles,
-                             int steps, bool check, hipStream_t s) {
-    return sweep::launch_tb<f64::Cell, TbShape<double>::rows, TbShape<double>::halo,
-                             TbShape<double>::threads, true>(a, tiles, n_tiles, steps,
-                                                                     check, s);
+                             int steps, bool check, int variant, hipStream_t s) {
+    return sweep::launch_tb_variant<f64::Cell>(a, tiles, n_tiles, steps, check, variant, s);
+}
+
+template <>
+hipError_t launch_tb_batch<double>(const SweepArgs<double> *args, const int32_t *lat,
+                                   const int32_t *tiles, int n_items, int steps, int variant,
+                                   hipStream_t s) {
+    return sweep::launch_tb_batch_variant<f64::Cell>(args, lat, tiles, n_items, steps, variant,
+                                                     s);
+}
+
+template <>
+hipError_t launch_step_batch<double>(const SweepArgs<double> *args, const int32_t *lat,
+                                     const int32_t *blocks, int n_items, hipStream_t s) {
+    return sweep::launch_step_batch<f64::Cell>(args, lat, blocks, n_items, s);
 }
 
 template <>

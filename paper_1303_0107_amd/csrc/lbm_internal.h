@@ -108,47 +108,61 @@ hipError_t launch_sweep(const SweepArgs<T> &a, bool check, hipStream_t s);
 
 // Temporal blocking: regions of 64 x rows cells with a halo of `halo` cells
 // (so up to `halo` steps per launch), tiles of (64 - 2 halo) x (rows - 2 halo)
-// cells, `threads` threads per workgroup, two LDS copies of the region
-// (9 * 64 * rows * sizeof(T) bytes each).
-template <typename T>
-struct TbShape;
-#ifndef LBM_TB32_ROWS
-#define LBM_TB32_ROWS 32
-#endif
-#ifndef LBM_TB32_HALO
-#define LBM_TB32_HALO 8
-#endif
-#ifndef LBM_TB64_ROWS
-#define LBM_TB64_ROWS 16
-#endif
-#ifndef LBM_TB64_HALO
-#define LBM_TB64_HALO 4
-#endif
-template <>
-struct TbShape<float> {
-    static constexpr int rows = LBM_TB32_ROWS, halo = LBM_TB32_HALO, threads = 1024;
-};
-template <>
-struct TbShape<double> {
-    static constexpr int rows = LBM_TB64_ROWS, halo = LBM_TB64_HALO, threads = 1024;
-};
-template <>
-struct TbShape<h16> {
-    static constexpr int rows = 32, halo = 8, threads = 1024;
-};
-template <>
-struct TbShape<bf16> {
-    static constexpr int rows = 32, halo = 8, threads = 1024;
+// cells, 1024 threads per workgroup, two LDS copies of the region
+// (9 * 64 * rows * sizeof(T) bytes each) and, in the compacted form, a list
+// of the region's non-solid cells (4 bytes per region cell); at most 160 KB
+// in all.  A few shapes are compiled per storage type; variant 0 is the
+// default, the autotuner may pick another.  The shape never changes the
+// results, only the speed.
+struct TbVariant {
+    int rows, halo;
+    bool compact;
 };
 template <typename T>
-constexpr int tile_w() { return 64 - 2 * TbShape<T>::halo; }
+struct TbVariants;
+template <>
+struct TbVariants<double> {
+    static constexpr int count = 3;
+    static constexpr TbVariant v[3] = {{16, 4, true}, {16, 4, false}, {16, 2, true}};
+};
+template <>
+struct TbVariants<float> {
+    static constexpr int count = 4;
+    static constexpr TbVariant v[4] = {{32, 8, true}, {32, 8, false}, {32, 4, true}, {16, 4, true}};
+};
+template <>
+struct TbVariants<h16> {
+    static constexpr int count = 4;
+    static constexpr TbVariant v[4] = {{32, 8, true}, {32, 8, false}, {32, 4, true}, {16, 4, true}};
+};
+template <>
+struct TbVariants<bf16> {
+    static constexpr int count = 4;
+    static constexpr TbVariant v[4] = {{32, 8, true}, {32, 8, false}, {32, 4, true}, {16, 4, true}};
+};
+constexpr int kTbThreads = 1024;
 template <typename T>
-constexpr int tile_h() { return TbShape<T>::rows - 2 * TbShape<T>::halo; }
-// `steps` (1..TbShape<T>::halo) time steps on the listed tiles; with `check` the last
-// step also writes per-tile residual partials (4 doubles per tile).
+constexpr int tile_w(int variant) { return 64 - 2 * TbVariants<T>::v[variant].halo; }
+template <typename T>
+constexpr int tile_h(int variant) {
+    return TbVariants<T>::v[variant].rows - 2 * TbVariants<T>::v[variant].halo;
+}
+// `steps` (1..halo) time steps on the listed tiles with region shape
+// `variant`; with `check` the last step also writes per-tile residual
+// partials (4 doubles per tile).
 template <typename T>
 hipError_t launch_tb(const SweepArgs<T> &a, const int32_t *tiles, int n_tiles, int steps,
-                     bool check, hipStream_t s);
+                     bool check, int variant, hipStream_t s);
+// The same for many lattices at once: item b is tile tiles[b] of lattice
+// lat[b] with arguments args[lat[b]] (device arrays); no residual partials.
+template <typename T>
+hipError_t launch_tb_batch(const SweepArgs<T> *args, const int32_t *lat, const int32_t *tiles,
+                           int n_items, int steps, int variant, hipStream_t s);
+// One time step of many lattices: item b is the 64 x 4 block blocks[b] of
+// lattice lat[b] with arguments args[lat[b]] (device arrays).
+template <typename T>
+hipError_t launch_step_batch(const SweepArgs<T> *args, const int32_t *lat,
+                             const int32_t *blocks, int n_items, hipStream_t s);
 int64_t sweep_blocks(int nx, int ny);
 hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
                             hipStream_t s);
@@ -194,7 +208,14 @@ template <>
 hipError_t launch_sweep<double>(const SweepArgs<double> &a, bool check, hipStream_t s);
 template <>
 hipError_t launch_tb<double>(const SweepArgs<double> &a, const int32_t *tiles, int n_tiles,
-                             int steps, bool check, hipStream_t s);
+                             int steps, bool check, int variant, hipStream_t s);
+template <>
+hipError_t launch_tb_batch<double>(const SweepArgs<double> *args, const int32_t *lat,
+                                   const int32_t *tiles, int n_items, int steps, int variant,
+                                   hipStream_t s);
+template <>
+hipError_t launch_step_batch<double>(const SweepArgs<double> *args, const int32_t *lat,
+                                     const int32_t *blocks, int n_items, hipStream_t s);
 template <>
 hipError_t launch_macro<double>(const MacroArgs<double> &a, hipStream_t s);
 template <>
@@ -222,7 +243,14 @@ hipError_t launch_import_plane<double>(double *f, const uint16_t *cell, const do
     hipError_t launch_sweep<T>(const SweepArgs<T> &a, bool check, hipStream_t s);          \
     template <>                                                                            \
     hipError_t launch_tb<T>(const SweepArgs<T> &a, const int32_t *tiles, int n_tiles,      \
-                            int steps, bool check, hipStream_t s);                         \
+                            int steps, bool check, int variant, hipStream_t s);            \
+    template <>                                                                            \
+    hipError_t launch_tb_batch<T>(const SweepArgs<T> *args, const int32_t *lat,            \
+                                  const int32_t *tiles, int n_items, int steps,            \
+                                  int variant, hipStream_t s);                             \
+    template <>                                                                            \
+    hipError_t launch_step_batch<T>(const SweepArgs<T> *args, const int32_t *lat,          \
+                                    const int32_t *blocks, int n_items, hipStream_t s);    \
     template <>                                                                            \
     hipError_t launch_rest_cells<T>(T * f, size_t plane, const int32_t *cells, int count,  \
                                     int nx, int pitch, hipStream_t s);                     \

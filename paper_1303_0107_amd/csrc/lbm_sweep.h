@@ -80,12 +80,13 @@ __device__ __forceinline__ void check_terms(const SweepArgs<T> &a, size_t n,
     a.uprev[a.plane + n] = uy;
 }
 
+// One time step of the 64 x 4 cells of block (bx, by).
 template <class Cell, bool CHECK>
-__global__ __launch_bounds__(256) void step_kernel(SweepArgs<typename Cell::T> a) {
-    using T = typename Cell::T;
+__device__ __forceinline__ void step_body(const SweepArgs<typename Cell::T> &a, const int bx,
+                                          const int by, double *part_out) {
     using CT = typename Cell::CT;
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int x = bx * 64 + threadIdx.x;
+    const int y = by * 4 + threadIdx.y;
     const bool in = x < a.nx && y < a.ny;
     const size_t n = (size_t)(in ? y : 0) * a.pitch + (in ? x : 0);
     const uint32_t cw = in ? a.cell[n] : 0u;
@@ -110,11 +111,31 @@ __global__ __launch_bounds__(256) void step_kernel(SweepArgs<typename Cell::T> a
     if (CHECK) {
         block_sum<4, 256>(part);
         if (threadIdx.x == 0 && threadIdx.y == 0) {
-            const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a.partials[b * 4 + k] = part[k];
+            for (int k = 0; k < 4; ++k) part_out[k] = part[k];
         }
     }
+}
+
+template <class Cell, bool CHECK>
+__global__ __launch_bounds__(256) void step_kernel(SweepArgs<typename Cell::T> a) {
+    step_body<Cell, CHECK>(
+        a, blockIdx.x, blockIdx.y,
+        CHECK ? a.partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 : nullptr);
+}
+
+// One time step of many lattices: work item b is the 64 x 4 block
+// blocks[b] (packed block row << 16 | block column) of lattice lat[b];
+// lat[b] < 0 marks a padding item.
+template <class Cell>
+__global__ __launch_bounds__(256) void step_batch_kernel(
+    const SweepArgs<typename Cell::T> *__restrict__ args, const int32_t *__restrict__ lat,
+    const int32_t *__restrict__ blocks) {
+    const int l = lat[blockIdx.x];
+    if (l < 0) return;
+    const SweepArgs<typename Cell::T> a = args[l];
+    const int t = blocks[blockIdx.x];
+    step_body<Cell, false>(a, t & 0xffff, t >> 16, nullptr);
 }
 
 // Temporal blocking.  Tile t = tiles[blockIdx.x] packs (tile row << 16 | tile
@@ -125,9 +146,8 @@ __global__ __launch_bounds__(256) void step_kernel(SweepArgs<typename Cell::T> a
 // the barrier).  Otherwise one copy updated in place: every thread keeps its
 // cells' new populations in registers until all reads of the step are done.
 template <class Cell, int RH, int H, int NT, bool PP, bool CHECK>
-__global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
-                                                const int32_t *__restrict__ tiles,
-                                                int steps) {
+__device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, const int t,
+                                        const int steps, double *part_out) {
     using T = typename Cell::T;
     using CT = typename Cell::CT;
     constexpr int RW = 64, IW = RW - 2 * H, IH = RH - 2 * H;
@@ -136,7 +156,6 @@ __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *L = reinterpret_cast<T *>(lds_raw);
 
-    const int t = tiles[blockIdx.x];
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gx = ox + lane;
@@ -215,9 +234,192 @@ __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
         block_sum<4, NT>(part);
         if (threadIdx.x == 0) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a.partials[(size_t)blockIdx.x * 4 + k] = part[k];
+            for (int k = 0; k < 4; ++k) part_out[k] = part[k];
         }
     }
+}
+
+// Temporal blocking with a compacted cell list.  On sparse geometries most
+// lanes of a region row hold solid cells, so the dense form above issues
+// every wave instruction for a few useful lanes.  Here, after the region is
+// in LDS, the workgroup lists its non-solid cells (LDS position and cell
+// word) ordered by class k = min(depth, H), largest first, where depth is
+// the distance to the region edge: a cell can be advanced at step s exactly
+// when depth >= s, and is a tile cell exactly when depth >= H.  So at every
+// step the cells to update are a prefix of the list, and consecutive lanes
+// take consecutive entries.  Within a class, entries keep row-major order.
+// Each update reads the same nine values as the dense form, so the results
+// are the same bits.  LDS: the two region copies, then PL list words.
+template <class Cell, int RH, int H, int NT, bool CHECK>
+__device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T> &a, const int t,
+                                                const int steps, double *part_out) {
+    using T = typename Cell::T;
+    using CT = typename Cell::CT;
+    constexpr int RW = 64, IW = RW - 2 * H, IH = RH - 2 * H;
+    constexpr int NW = NT / 64, CPT = RH / NW, PL = RW * RH;
+    static_assert(RH % NW == 0, "region rows must split evenly over waves");
+    static_assert(PL <= 65536 && RH <= 64, "list entries pack the position in 16 bits");
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *L = reinterpret_cast<T *>(lds_raw);
+    uint32_t *list = reinterpret_cast<uint32_t *>(lds_raw + (size_t)2 * 9 * PL * sizeof(T));
+    __shared__ int row_off[RH][H];  // per row and class: count, then offset
+    __shared__ int cls_total[H + 1];
+    __shared__ int cls_base[H + 2];
+
+    const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gx = ox + lane;
+    const bool col_in = gx >= 0 && gx < a.nx;
+    const uint64_t below = (1ull << lane) - 1ull;
+
+    int cls[CPT];
+    uint32_t cw[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int ry = wave + c * NW, gy = oy + ry;
+        const bool in = col_in && gy >= 0 && gy < a.ny;
+        const size_t n = in ? (size_t)gy * a.pitch + gx : 0;
+        cw[c] = in ? a.cell[n] : 0u;
+        const bool live = in && (cw[c] >> 8) != kSolid;
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            L[i * PL + ry * RW + lane] = live ? a.fin[(size_t)i * a.plane + n] : Cell::store(CT(0));
+        const int depth = min(min(lane, RW - 1 - lane), min(ry, RH - 1 - ry));
+        cls[c] = live ? min(depth, H) : 0;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            const uint64_t m = __ballot(cls[c] == k);
+            if (lane == 0) row_off[ry][k - 1] = __popcll(m);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < H) {  // one thread per class: exclusive scan over rows
+        const int k = threadIdx.x;
+        int run = 0;
+        for (int r = 0; r < RH; ++r) {
+            const int v = row_off[r][k];
+            row_off[r][k] = run;
+            run += v;
+        }
+        cls_total[k + 1] = run;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // classes in decreasing order; cls_base[k] = entries of class > k
+        int run = 0;
+        cls_base[H + 1] = 0;
+        for (int k = H; k >= 1; --k) {
+            cls_base[k] = run;
+            run += cls_total[k];
+        }
+        cls_base[0] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int ry = wave + c * NW;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            const uint64_t m = __ballot(cls[c] == k);
+            if (cls[c] == k)
+                list[cls_base[k] + row_off[ry][k - 1] + __popcll(m & below)] =
+                    (cw[c] << 16) | (uint32_t)(ry * RW + lane);
+        }
+    }
+    __syncthreads();
+    const int n_all = cls_base[0];
+    uint32_t ent[CPT];
+#pragma unroll
+    for (int m = 0; m < CPT; ++m) {
+        const int j = threadIdx.x + m * NT;
+        ent[m] = j < n_all ? list[j] : 0u;
+    }
+
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    int src_buf = 0;
+    for (int s = 1; s <= steps; ++s) {
+        const bool last = s == steps;
+        // cells of class >= s, or the tile cells (class H) at the last step
+        const int n_s = last ? cls_base[H - 1 + 1] + cls_total[H] : cls_base[s] + cls_total[s];
+        const T *Ls = L + src_buf * 9 * PL;
+        T *Ld = L + (1 - src_buf) * 9 * PL;
+#pragma unroll
+        for (int m = 0; m < CPT; ++m) {
+            if (threadIdx.x + m * NT < n_s) {
+                const uint32_t e = ent[m];
+                const uint32_t c = e >> 16;
+                const int pos = (int)(e & 0xffffu);
+                const int ry = pos / RW, lx = pos % RW;
+                const uint32_t type = c >> 8;
+                CT f[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const bool wall = i > 0 && ((c >> (i - 1)) & 1u);
+                    const int src = wall ? kOpp[i] * PL + pos : i * PL + pos - kCy[i] * RW - kCx[i];
+                    f[i] = Cell::load(Ls[src]);
+                }
+                double mass, ux, uy;
+                const int gy = oy + ry;
+                Cell::update(f, type, type == kInlet ? (CT)a.uin[gy] : CT(0), a, mass, ux, uy);
+                if (last) {
+                    const size_t n = (size_t)gy * a.pitch + (ox + lx);
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) a.fout[(size_t)i * a.plane + n] = Cell::store(f[i]);
+                    if (CHECK) check_terms(a, n, mass, ux, uy, part);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) Ld[i * PL + pos] = Cell::store(f[i]);
+                }
+            }
+        }
+        if (last) break;
+        __syncthreads();
+        src_buf = 1 - src_buf;
+    }
+    if (CHECK) {
+        block_sum<4, NT>(part);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) part_out[k] = part[k];
+        }
+    }
+}
+
+// One region shape: rows x 64 cells, halo H, dense or compacted.
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK>
+__device__ __forceinline__ void tb_dispatch(const SweepArgs<typename Cell::T> &a, const int t,
+                                            const int steps, double *part_out) {
+    if constexpr (COMPACT)
+        tb_body_compact<Cell, RH, H, NT, CHECK>(a, t, steps, part_out);
+    else
+        tb_body<Cell, RH, H, NT, PP, CHECK>(a, t, steps, part_out);
+}
+
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK>
+__global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
+                                                const int32_t *__restrict__ tiles,
+                                                int steps) {
+    tb_dispatch<Cell, RH, H, NT, PP, COMPACT, CHECK>(
+        a, tiles[blockIdx.x], steps, CHECK ? a.partials + (size_t)blockIdx.x * 4 : nullptr);
+}
+
+// Many lattices in one launch: work item b is tile tiles[b] of lattice
+// lat[b], whose arguments are args[lat[b]]; lat[b] < 0 marks a padding item
+// (the whole workgroup leaves at once, before any barrier).
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT>
+__global__ __launch_bounds__(NT) void tb_batch_kernel(
+    const SweepArgs<typename Cell::T> *__restrict__ args, const int32_t *__restrict__ lat,
+    const int32_t *__restrict__ tiles, int steps) {
+    const int l = lat[blockIdx.x];
+    if (l < 0) return;
+    const SweepArgs<typename Cell::T> a = args[l];
+    tb_dispatch<Cell, RH, H, NT, PP, COMPACT, false>(a, tiles[blockIdx.x], steps, nullptr);
+}
+
+// Dynamic LDS of one region shape.
+template <typename T, int RH, bool PP, bool COMPACT>
+constexpr size_t tb_lds_bytes() {
+    return (size_t)((PP || COMPACT) ? 2 : 1) * 9 * 64 * RH * sizeof(T) +
+           (COMPACT ? (size_t)64 * RH * sizeof(uint32_t) : 0);
 }
 
 // Host-side launch helpers shared by the per-precision units.
@@ -231,14 +433,14 @@ hipError_t launch_step(const SweepArgs<typename Cell::T> &a, bool check, hipStre
     return hipGetLastError();
 }
 
-template <class Cell, int RH, int H, int NT, bool PP>
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT>
 hipError_t launch_tb(const SweepArgs<typename Cell::T> &a, const int32_t *tiles, int n_tiles,
                      int steps, bool check, hipStream_t s) {
     if (n_tiles <= 0 || steps <= 0) return hipSuccess;
     if (steps > H) return hipErrorInvalidValue;
-    const size_t lds = (size_t)(PP ? 2 : 1) * 9 * 64 * RH * sizeof(typename Cell::T);
-    auto k_plain = tb_kernel<Cell, RH, H, NT, PP, false>;
-    auto k_check = tb_kernel<Cell, RH, H, NT, PP, true>;
+    const size_t lds = tb_lds_bytes<typename Cell::T, RH, PP, COMPACT>();
+    auto k_plain = tb_kernel<Cell, RH, H, NT, PP, COMPACT, false>;
+    auto k_check = tb_kernel<Cell, RH, H, NT, PP, COMPACT, true>;
     static bool configured = false;
     if (!configured) {
         hipError_t e = hipFuncSetAttribute((const void *)k_plain,
@@ -254,6 +456,66 @@ hipError_t launch_tb(const SweepArgs<typename Cell::T> &a, const int32_t *tiles,
     else
         hipLaunchKernelGGL(k_plain, dim3((unsigned)n_tiles), dim3(NT), lds, s, a, tiles, steps);
     return hipGetLastError();
+}
+
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT>
+hipError_t launch_tb_batch(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
+                           const int32_t *tiles, int n_items, int steps, hipStream_t s) {
+    if (steps > H) return hipErrorInvalidValue;
+    const size_t lds = tb_lds_bytes<typename Cell::T, RH, PP, COMPACT>();
+    auto k = tb_batch_kernel<Cell, RH, H, NT, PP, COMPACT>;
+    static bool configured = false;
+    if (!configured) {  // also on an empty call, so that it can precede a graph capture
+        const hipError_t e = hipFuncSetAttribute(
+            (const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        configured = true;
+    }
+    if (n_items <= 0 || steps <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k, dim3((unsigned)n_items), dim3(NT), lds, s, args, lat, tiles, steps);
+    return hipGetLastError();
+}
+
+template <class Cell>
+hipError_t launch_step_batch(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
+                             const int32_t *blocks, int n_items, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL((step_batch_kernel<Cell>), dim3((unsigned)n_items), dim3(64, 4), 0, s,
+                       args, lat, blocks);
+    return hipGetLastError();
+}
+
+// Run-time choice among the compiled region shapes of the storage type.
+template <class Cell, int V = 0>
+hipError_t launch_tb_variant(const SweepArgs<typename Cell::T> &a, const int32_t *tiles,
+                             int n_tiles, int steps, bool check, int variant, hipStream_t s) {
+    using T = typename Cell::T;
+    if constexpr (V < TbVariants<T>::count) {
+        if (variant == V)
+            return launch_tb<Cell, TbVariants<T>::v[V].rows, TbVariants<T>::v[V].halo,
+                             kTbThreads, true, TbVariants<T>::v[V].compact>(a, tiles, n_tiles,
+                                                                            steps, check, s);
+        return launch_tb_variant<Cell, V + 1>(a, tiles, n_tiles, steps, check, variant, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <class Cell, int V = 0>
+hipError_t launch_tb_batch_variant(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
+                                   const int32_t *tiles, int n_items, int steps, int variant,
+                                   hipStream_t s) {
+    using T = typename Cell::T;
+    if constexpr (V < TbVariants<T>::count) {
+        if (variant == V)
+            return launch_tb_batch<Cell, TbVariants<T>::v[V].rows, TbVariants<T>::v[V].halo,
+                                   kTbThreads, true, TbVariants<T>::v[V].compact>(
+                args, lat, tiles, n_items, steps, s);
+        return launch_tb_batch_variant<Cell, V + 1>(args, lat, tiles, n_items, steps, variant,
+                                                    s);
+    } else {
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace sweep

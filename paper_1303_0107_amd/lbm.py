@@ -97,6 +97,16 @@ def load() -> ctypes.CDLL:
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_bench_sweep": (ctypes.c_int, [H, i32, P]),
         "lbm_profile_sweeps": (ctypes.c_int, [H, i32, P, P, P]),
+        "lbm_tb_variant_count": (i32, [i32]),
+        "lbm_tb_variant_info": (ctypes.c_int, [i32, i32, P, P, P, P]),
+        "lbm_set_tb_variant": (ctypes.c_int, [H, i32]),
+        "lbm_autotune": (ctypes.c_int, [H, i32, P, P, i32]),
+        "lbm_batch_create": (ctypes.c_int, [P, i32, P, ctypes.POINTER(H)]),
+        "lbm_batch_run": (ctypes.c_int, [H, i64, P]),
+        "lbm_batch_configure": (ctypes.c_int, [H, i32, i32]),
+        "lbm_batch_tune": (ctypes.c_int, [H, i32, P, P, P, i32]),
+        "lbm_batch_info": (ctypes.c_int, [H, P, P, P]),
+        "lbm_batch_destroy": (None, [H]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -251,6 +261,73 @@ def lbm_profile_sweeps(h, enable: bool):
     return n.value, k.value, ms.value
 
 
+def lbm_tb_variant_count(precision: int) -> int:
+    return int(load().lbm_tb_variant_count(int(precision)))
+
+
+def lbm_tb_variant_info(precision: int, variant: int):
+    """(rows, halo, tile_w, tile_h) of a compiled region shape."""
+    v = [ctypes.c_int32(0) for _ in range(4)]
+    _check(load().lbm_tb_variant_info(int(precision), int(variant),
+                                      *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def lbm_set_tb_variant(h, variant: int) -> None:
+    _check(load().lbm_set_tb_variant(h, int(variant)))
+
+
+def lbm_autotune(h, trial_steps: int, n_variants: int):
+    """Returns (best shape, ms per step of each shape)."""
+    best = ctypes.c_int32(0)
+    ms = np.zeros(n_variants, dtype=np.float64)
+    _check(load().lbm_autotune(h, int(trial_steps), ctypes.byref(best), _p(ms), n_variants))
+    return best.value, ms
+
+
+def lbm_batch_create(handles, stream=None):
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    out = ctypes.c_void_p()
+    _check(load().lbm_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(handles), stream,
+                                   ctypes.byref(out)))
+    return out
+
+
+def lbm_batch_run(b, steps: int) -> float:
+    """Advance every member; returns the elapsed milliseconds of the launches."""
+    ms = ctypes.c_double(0.0)
+    _check(load().lbm_batch_run(b, int(steps), ctypes.byref(ms)))
+    return ms.value
+
+
+def lbm_batch_configure(b, variant: int, order: int) -> None:
+    _check(load().lbm_batch_configure(b, int(variant), int(order)))
+
+
+def lbm_batch_tune(b, trial_steps: int, n_variants: int):
+    """n_variants = shape count + 1 (the single-step mode).  Returns (best
+    variant, best order, ms per step of configuration 2*variant+order)."""
+    bv = ctypes.c_int32(0)
+    bo = ctypes.c_int32(0)
+    ms = np.zeros(2 * n_variants, dtype=np.float64)
+    _check(load().lbm_batch_tune(b, int(trial_steps), ctypes.byref(bv), ctypes.byref(bo),
+                                 _p(ms), 2 * n_variants))
+    return bv.value, bo.value, ms
+
+
+def lbm_batch_info(b):
+    """(tiles per launch, steps per launch, summed non-solid cells)."""
+    items = ctypes.c_int64(0)
+    spl = ctypes.c_int32(0)
+    cells = ctypes.c_int64(0)
+    _check(load().lbm_batch_info(b, ctypes.byref(items), ctypes.byref(spl), ctypes.byref(cells)))
+    return items.value, spl.value, cells.value
+
+
+def lbm_batch_destroy(b) -> None:
+    load().lbm_batch_destroy(b)
+
+
 class Lattice:
     """Owning wrapper of one handle."""
 
@@ -260,6 +337,7 @@ class Lattice:
         if types is not None:
             ny, nx = types.shape
         self.nx, self.ny = int(nx), int(ny)
+        self.precision = int(precision)
         self.desc = make_desc(self.nx, self.ny, tau, u_peak, rho_out, precision, levels, widths)
         if stream is None:
             stream = current_stream_handle()
@@ -306,3 +384,43 @@ class Lattice:
 
     def profile_sweeps(self, enable):
         return lbm_profile_sweeps(self.h, enable)
+
+    def set_tb_variant(self, variant):
+        lbm_set_tb_variant(self.h, variant)
+
+    def autotune(self, trial_steps):
+        return lbm_autotune(self.h, trial_steps, lbm_tb_variant_count(self.precision))
+
+
+class Batch:
+    """Owning wrapper of a batch; keeps its member Lattice objects alive."""
+
+    def __init__(self, lattices, stream=None):
+        self.members = list(lattices)
+        if stream is None:
+            stream = current_stream_handle()
+        self.precision = self.members[0].precision if self.members else LBM_F64
+        self.b = lbm_batch_create([m.h for m in self.members], stream)
+
+    def close(self):
+        if self.b:
+            lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, steps):
+        return lbm_batch_run(self.b, steps)
+
+    def configure(self, variant, order):
+        lbm_batch_configure(self.b, variant, order)
+
+    def tune(self, trial_steps):
+        return lbm_batch_tune(self.b, trial_steps, lbm_tb_variant_count(self.precision) + 1)
+
+    def info(self):
+        return lbm_batch_info(self.b)

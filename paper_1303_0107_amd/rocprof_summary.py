@@ -14,11 +14,18 @@ import csv
 
 
 def per_kernel(path, counter):
+    """Mean counter value per (kernel, grid size), dispatch counts, and the
+    largest single value read by the plain copy kernel."""
     agg = collections.defaultdict(list)
+    copy_max = 0.0
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
-            agg[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()}
+            v = float(r["Counter_Value"])
+            agg[(r["Kernel_Name"], int(r["Grid_Size"]))].append(v)
+            if "copyBuffer" in r["Kernel_Name"]:
+                copy_max = max(copy_max, v)
+    return ({k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()},
+            copy_max)
 
 
 def main():
@@ -42,11 +49,11 @@ def main():
         return
     print()
     print(f"counters: {a.pmc_cmd}")
-    fetch, nf = per_kernel(a.fetch, "FETCH_SIZE")
-    write, nw = per_kernel(a.write, "WRITE_SIZE")
+    # The copy of --copy-bytes is the largest copy the program makes, so it
+    # is the copy dispatch with the largest reading.
+    fetch, nf, copy_f = per_kernel(a.fetch, "FETCH_SIZE")
+    write, nw, copy_w = per_kernel(a.write, "WRITE_SIZE")
     kib = 1024.0
-    copy_f = max(v for (k, g), v in fetch.items() if "copyBuffer" in k)
-    copy_w = max(v for (k, g), v in write.items() if "copyBuffer" in k)
     sf = a.copy_bytes / (copy_f * kib)
     sw = a.copy_bytes / (copy_w * kib)
     print(f"plain copy of {a.copy_bytes} B: FETCH_SIZE {copy_f:.1f} KiB, WRITE_SIZE {copy_w:.1f} KiB"
