@@ -201,6 +201,125 @@ def bench_batch(args) -> int:
     return 0
 
 
+SERVE_WORKLOAD = "serve-poisson-50rps"
+
+
+def bench_serve(args) -> int:
+    """Serving: Poisson arrivals of solve / optimise requests (FP32 and FP16
+    offset storage) submitted in real time to the request server (continuous
+    batching, admission by HBM footprint).  value = aggregate lattice updates
+    per second (all cells of every request times its steps) over the wall
+    time from the first arrival to the last completion; latency = completion
+    minus submission per request, p50 / p99.  roofline: whole rounds (batched
+    sweeps plus the host work of events), algorithmic bytes of the steps
+    taken over the time spent in rounds -- a lower bound on the kernels'
+    rate, not a kernel measurement."""
+    import numpy as np
+    import torch
+
+    from paper_1303_0107_amd import inputs as I
+    from paper_1303_0107_amd import lbm
+
+    reqs = I.serving_requests(rate=args.serve_rate, seconds=args.serve_seconds, seed=5)
+    prec = {"f32": lbm.LBM_F32, "f16": lbm.LBM_F32_S_F16}
+    s_bytes = {"f32": 4, "f16": 2}
+    print(f"# {SERVE_WORKLOAD}: {len(reqs)} requests over {args.serve_seconds} s",
+          file=sys.stderr, flush=True)
+    crs = []
+    nns = []
+    for q in reqs:
+        w = q.workload
+        kind = lbm.LBM_REQ_SOLVE if q.kind == "solve" else lbm.LBM_REQ_OPTIMIZE
+        crs.append(lbm.make_request(w.nx, w.ny, w.levels, w.widths, w.tau, w.u_peak,
+                                    prec[q.storage], kind, solve_steps=q.solve_steps,
+                                    iterations=q.iterations,
+                                    steps_per_iteration=q.steps_per_iteration,
+                                    frac=0.01, seed=q.seed))
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    srv = lbm.Server(hbm_budget=budget, max_sessions=args.max_sessions, quantum=args.quantum,
+                     variant=-1, order=1)
+    torch.cuda.synchronize()
+    results = {}
+    ids = {}
+    t0 = time.perf_counter()
+    last_print = t0
+    for k, q in enumerate(reqs):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= q.t:
+                break
+            for r in srv.poll(cap=256, wait_ms=max(1, int((q.t - now) * 1e3))):
+                results[r.id] = r
+        ids[srv.submit(crs[k])] = k
+        if time.perf_counter() - last_print > 10:
+            last_print = time.perf_counter()
+            print(f"# t={last_print - t0:.0f}s submitted {k + 1} done {len(results)}",
+                  file=sys.stderr, flush=True)
+    srv.drain()
+    for r in srv.poll(cap=len(reqs) + 8):
+        results[r.id] = r
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    res = [results[i] for i in sorted(results)]
+    bad = [r for r in res if r.status != lbm.LBM_OK]
+    lat = np.array([r.t_done - r.t_submit for r in res]) * 1e3
+    queue = np.array([r.t_admit - r.t_submit for r in res]) * 1e3
+    mlups = st.cell_steps / wall / 1e6
+    # algorithmic bytes of the steps taken (per request: 18 s N_ns + N per step)
+    algo = 0.0
+    for r in res:
+        q = reqs[ids[r.id]]
+        algo += r.steps * (18 * s_bytes[q.storage] * r.stats.n_nonsolid + r.cells)
+    achieved = algo / st.busy_seconds / 1e9 if st.busy_seconds > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 0,
+        "ms_per_step": round(wall / max(len(reqs), 1) * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": SERVE_WORKLOAD, "requests": len(reqs),
+            "arrivals": f"Poisson {args.serve_rate}/s for {args.serve_seconds} s, seed 5",
+            "lattices": "nx = 64 round(256 2^U(0,4) / 64), ny = nx/2; generator as the "
+                        "batched candidates",
+            "mix": "FP32 / FP16 offset storage 50/50 (arithmetic f64 / f32); solve 500 steps / "
+                   "optimise 100 steps + 20 x (exchange step + 40 steps), 50/50",
+            "hbm_budget_gb": args.hbm_budget_gb, "max_sessions": args.max_sessions,
+            "quantum": args.quantum,
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
+                           "p99": round(float(np.percentile(lat, 99)), 2),
+                           "mean": round(float(lat.mean()), 2),
+                           "max": round(float(lat.max()), 2)},
+            "queue_ms": {"p50": round(float(np.percentile(queue, 50)), 2),
+                         "p99": round(float(np.percentile(queue, 99)), 2)},
+            "failed": len(bad), "rounds": st.rounds, "busy_seconds": round(st.busy_seconds, 3),
+            "admit_seconds": round(st.admit_seconds, 3),
+            "sweep_seconds": round(st.sweep_seconds, 3),
+            "event_seconds": round(st.event_seconds, 3),
+            "wall_seconds": round(wall, 3), "peak_bytes": st.peak_bytes,
+            "mflups": round(st.nonsolid_cell_steps / wall / 1e6, 2),
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "server rounds (batched sweeps + event host work), not a single kernel",
+        },
+    }
+    if not args.no_cpu:
+        w = I.HEADLINE_1024x512
+        out["cpu_baseline"] = cpu_baseline(w.types(), w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0 if not bad else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +340,11 @@ def main() -> int:
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--tune-steps", type=int, default=256,
                     help="steps per autotuner trial (batched workload)")
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--hbm-budget-gb", type=float, default=32.0)
+    ap.add_argument("--max-sessions", type=int, default=64)
+    ap.add_argument("--quantum", type=int, default=20)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -239,6 +363,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload == BATCH_WORKLOAD:
         return bench_batch(args)
+    if args.workload == SERVE_WORKLOAD:
+        return bench_serve(args)
     w = workloads()[args.workload]
     types = w.types()
     N = types.size

@@ -339,6 +339,115 @@ int lbm_batch_info(lbm_batch *b, int64_t *items, int32_t *steps_per_launch,
 /* Release a batch (the member handles are untouched; NULL is ignored). */
 void lbm_batch_destroy(lbm_batch *b);
 
+/* Switch the captured-graph replay of a batch's time loop on (default) or
+ * off; off suits batches whose membership changes every few runs, where a
+ * capture would be used too few times to pay for itself.  Results do not
+ * change.  Errors: LBM_EINVAL. */
+int lbm_batch_set_graphs(lbm_batch *b, int32_t enable);
+
+/*
+ * 64-bit digest of the current state and mask: the sum, modulo 2^64, over
+ * every non-solid cell n and population i of SplitMix64 of the stored bits
+ * of f_i(n) mixed with (9 n + i), plus SplitMix64 of each cell's type mixed
+ * with its index.  Order-free, so it is the same however the work is split;
+ * two states with the same digest are the same bits (up to 64-bit hash
+ * collisions).  For comparing runs, not for security.
+ * Errors: LBM_EINVAL, LBM_EHIP.
+ */
+int lbm_state_digest(lbm_handle *h, uint64_t *digest);
+
+/*
+ * Serving: a request loop with continuous batching.  A worker thread owns
+ * the device work.  Requests wait in a FIFO queue and are admitted, in
+ * order, while the summed lbm_footprint_bytes of the admitted sessions stays
+ * within hbm_budget and fewer than max_sessions are active; an admitted
+ * request becomes a session whose lattice state stays on the device until it
+ * completes.  Rounds: every active session advances by the same number of
+ * time steps (at most `quantum`, fewer if a session's next event is nearer),
+ * all sessions of one precision in one lbm_batch; then sessions at an event
+ * take it (an optimise iteration's exchange step, or completion: outlet
+ * statistics and the state digest, after which the session's memory is
+ * released).  Requests that arrive while a round runs join at the next
+ * round.  Each session's results are the same bits as the same request run
+ * alone, because every lattice's arithmetic is independent of the others.
+ *
+ * Work of a request (Sec. 2.3): SOLVE advances the lattice from rest by
+ * solve_steps steps; OPTIMIZE advances solve_steps steps, then `iterations`
+ * times takes the exchange step (Sec. 2.2) with params.seed + iteration as
+ * the tie-break seed and advances steps_per_iteration steps.
+ */
+enum { LBM_REQ_SOLVE = 0, LBM_REQ_OPTIMIZE = 1 };
+
+typedef struct {
+    size_t hbm_budget;      /* bytes of lbm_footprint_bytes admitted at once   */
+    int32_t max_sessions;   /* active sessions at once (>= 1)                  */
+    int32_t quantum;        /* time steps per round at most (>= 1)             */
+    int32_t variant;        /* batch variant (lbm_batch_configure), -1: default */
+    int32_t order;          /* batch work-list order (0 or 1)                  */
+} lbm_server_config;
+
+typedef struct {
+    lbm_geometry_desc geom;  /* generator description (cell_types NULL)        */
+    int32_t kind;            /* LBM_REQ_SOLVE or LBM_REQ_OPTIMIZE               */
+    int32_t iterations;      /* exchange steps (OPTIMIZE), >= 0                 */
+    int64_t solve_steps;     /* steps from rest, >= 0                           */
+    int64_t steps_per_iteration; /* steps after each exchange step, >= 0        */
+    lbm_shape_params shape;  /* exchange-step parameters (OPTIMIZE)             */
+} lbm_request;
+
+typedef struct {
+    uint64_t id;             /* as returned by lbm_server_submit                */
+    int32_t status;          /* LBM_OK or the first error of the session        */
+    int32_t iterations_done;
+    int64_t steps;           /* time steps taken                                */
+    int64_t cells;           /* nx * ny                                         */
+    uint64_t digest;         /* lbm_state_digest at completion                  */
+    double t_submit, t_admit, t_done; /* seconds on a monotonic clock           */
+    lbm_stats stats;         /* lbm_outlet_stats at completion                  */
+} lbm_result;
+
+typedef struct {
+    int64_t submitted, completed, rejected, active, queued;
+    int64_t rounds;
+    int64_t cell_steps;      /* sum over sessions of nx * ny * steps taken      */
+    int64_t nonsolid_cell_steps;
+    double busy_seconds;     /* time in rounds (device work and host events)    */
+    double admit_seconds;    /* of which: creating admitted sessions            */
+    double sweep_seconds;    /*           batched sweeps (incl. batch rebuilds) */
+    double event_seconds;    /*           exchange steps and completions        */
+    size_t peak_bytes;       /* largest admitted footprint sum                  */
+} lbm_server_stats;
+
+typedef struct lbm_server lbm_server;
+
+/* Start a server (and its worker thread) on the current device, issuing work
+ * on hip_stream (borrowed; NULL: the null stream).
+ * Errors: LBM_EINVAL (config), LBM_ENOMEM, LBM_EHIP. */
+int lbm_server_create(const lbm_server_config *cfg, void *hip_stream,
+                      lbm_server **out);
+
+/* Queue a request (copied); *id receives its identifier (ids count up from
+ * 1).  A request whose footprint exceeds hbm_budget is not queued: it
+ * completes at once with status LBM_ENOMEM.  Errors: LBM_EINVAL (bad request
+ * or server stopped). */
+int lbm_server_submit(lbm_server *s, const lbm_request *req, uint64_t *id);
+
+/* Move up to `cap` completed results into `out`, waiting up to wait_ms
+ * milliseconds for the first one (0: no wait, < 0: wait until one arrives
+ * or nothing is pending).  Returns the number moved (>= 0) or an error. */
+int lbm_server_poll(lbm_server *s, lbm_result *out, int32_t cap, int32_t wait_ms);
+
+/* Block until every submitted request has completed (its result may still be
+ * waiting for lbm_server_poll). */
+int lbm_server_drain(lbm_server *s);
+
+/* Counters since creation. */
+int lbm_server_stats_get(lbm_server *s, lbm_server_stats *st);
+
+/* Stop the worker (pending and active requests are abandoned) and release
+ * everything (NULL is ignored). */
+void lbm_server_destroy(lbm_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,8 @@ SOURCES = {
     "lbm_kernels.hip": [],
     "lbm_f64.hip": ["-ffp-contract=off"],
     "lbm_api.hip": ["-ffp-contract=off"],
+    "lbm_serve.hip": [],
+    "lbm_select.hip": [],
 }
 
 

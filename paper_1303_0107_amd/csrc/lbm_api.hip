@@ -225,7 +225,7 @@ struct lbm_handle {
     int cur = 0;  // buffer holding the current state
     DeviceBuffer cell, types, uin, uprev, partials, red, out_rows, bnd;
     DeviceBuffer macro;  // 3*nx*ny doubles (rho, ux, uy), on demand
-    DeviceBuffer cand, sel;
+    DeviceBuffer cand, sel, select_tmp, removed_rho;
     int64_t cand_cap = 0;
     double *pinned = nullptr;  // small host staging for readbacks
     size_t pinned_bytes = 0;
@@ -257,7 +257,16 @@ struct lbm_handle {
     std::vector<int32_t> tile_host;
     int n_tiles = 0;
     int tb_variant = 0;         // region shape (index into the compiled shapes)
-    uint64_t mask_version = 0;  // bumped whenever the tile list is rebuilt
+    uint64_t mask_version = 0;  // bumped whenever the mask changes
+    // Non-solid cell counts per tile of a tw x th tiling and the tiles that
+    // hold one, row-major, packed (tile row << 16 | tile column); built once
+    // per tiling by a scan of the mask, then kept current from the cells each
+    // exchange step flips.
+    struct Tiling {
+        int tw = 0, th = 0, ntx = 0, nty = 0;
+        std::vector<int32_t> count, list;
+    };
+    std::vector<Tiling> tilings;
     int64_t prof_kernels = 0;
 
     size_t N() const { return (size_t)nx * ny; }
@@ -302,26 +311,6 @@ size_t max_tile_count(int nx, int ny, int precision) {
     return m;
 }
 
-// Tiles of a tw x th tiling whose cells include a non-solid one, packed as
-// (tile row << 16 | tile column).
-std::vector<int32_t> active_tiles(const std::vector<uint8_t> &types, int nx, int ny, int tw,
-                                  int th) {
-    const int ntx = (nx + tw - 1) / tw, nty = (ny + th - 1) / th;
-    std::vector<int32_t> out;
-    for (int ty = 0; ty < nty; ++ty)
-        for (int tx = 0; tx < ntx; ++tx) {
-            bool any = false;
-            for (int y = ty * th; y < std::min(ny, (ty + 1) * th) && !any; ++y)
-                for (int x = tx * tw; x < std::min(nx, (tx + 1) * tw); ++x)
-                    if (types[(size_t)y * nx + x] != LBM_SOLID) {
-                        any = true;
-                        break;
-                    }
-            if (any) out.push_back((ty << 16) | tx);
-        }
-    return out;
-}
-
 size_t footprint(int nx, int ny, int precision) {
     const int pitch = pitch_for(nx);
     const size_t plane = (size_t)ny * pitch, N = (size_t)nx * ny;
@@ -360,19 +349,59 @@ void compute_ports(lbm_handle *h) {
     }
 }
 
+void list_tiles(lbm_handle::Tiling &t) {
+    t.list.clear();
+    for (int ty = 0; ty < t.nty; ++ty)
+        for (int tx = 0; tx < t.ntx; ++tx)
+            if (t.count[(size_t)ty * t.ntx + tx] > 0) t.list.push_back((ty << 16) | tx);
+}
+
+// Tiles of a tw x th tiling that hold a non-solid cell (cached per tiling).
+const std::vector<int32_t> &tile_list(lbm_handle *h, int tw, int th) {
+    for (const auto &t : h->tilings)
+        if (t.tw == tw && t.th == th) return t.list;
+    lbm_handle::Tiling t;
+    t.tw = tw;
+    t.th = th;
+    t.ntx = (h->nx + tw - 1) / tw;
+    t.nty = (h->ny + th - 1) / th;
+    t.count.assign((size_t)t.ntx * t.nty, 0);
+    for (int y = 0; y < h->ny; ++y) {
+        const uint8_t *row = h->host_types.data() + (size_t)y * h->nx;
+        int32_t *c = t.count.data() + (size_t)(y / th) * t.ntx;
+        for (int tx = 0; tx < t.ntx; ++tx) {
+            int n = 0;
+            const int x1 = std::min(h->nx, (tx + 1) * tw);
+            for (int x = tx * tw; x < x1; ++x) n += row[x] != LBM_SOLID;
+            c[tx] += n;
+        }
+    }
+    list_tiles(t);
+    h->tilings.push_back(std::move(t));
+    return h->tilings.back().list;
+}
+
+// Cells made solid (removed) and fluid (added) by an exchange step.
+void tilings_flip(lbm_handle *h, const std::vector<int32_t> &removed,
+                  const std::vector<int32_t> &added) {
+    for (auto &t : h->tilings) {
+        for (int32_t n : removed) --t.count[(size_t)((n / h->nx) / t.th) * t.ntx + (n % h->nx) / t.tw];
+        for (int32_t n : added) ++t.count[(size_t)((n / h->nx) / t.th) * t.ntx + (n % h->nx) / t.tw];
+        list_tiles(t);
+    }
+}
+
 // Tiles of the temporal-blocking sweep (current shape) whose cells include a
 // non-solid one, uploaded to the device.
 void rebuild_tiles(lbm_handle *h) {
-    h->tile_host = active_tiles(h->host_types, h->nx, h->ny,
-                                tile_width(h->precision, h->tb_variant),
-                                tile_height(h->precision, h->tb_variant));
+    h->tile_host = tile_list(h, tile_width(h->precision, h->tb_variant),
+                             tile_height(h->precision, h->tb_variant));
     h->n_tiles = (int)h->tile_host.size();
     h->tiles.ensure(max_tile_count(h->nx, h->ny, h->precision) * sizeof(int32_t));
     if (h->n_tiles > 0)
         HIP_TRY(hipMemcpyAsync(h->tiles.p, h->tile_host.data(), h->n_tiles * sizeof(int32_t),
                                hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    ++h->mask_version;
 }
 
 // Parabolic inlet profile (Sec. 3.3) on each maximal run of inlet rows,
@@ -783,8 +812,8 @@ void build_work(lbm_batch *b) {
     const int th = one ? 4 : tile_height(b->precision, b->variant);
     std::vector<int32_t> L, Tl;
     for (size_t i = 0; i < b->hs.size(); ++i) {
-        const lbm_handle *h = b->hs[i];
-        for (int32_t t : active_tiles(h->host_types, h->nx, h->ny, tw, th)) {
+        lbm_handle *h = b->hs[i];
+        for (int32_t t : tile_list(h, tw, th)) {
             L.push_back((int32_t)i);
             Tl.push_back(t);
         }
@@ -1236,10 +1265,14 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
         if (keff > 0) {
             h->sel.ensure(2 * (size_t)keff * sizeof(int32_t));
             int32_t *srem = h->sel.as<int32_t>(), *sadd = srem + keff;
-            HIP_TRY(launch_rank(kf, hf, if_, (int64_t)cnt[0], keff, srem, h->stream));
-            HIP_TRY(launch_rank(ks, hs, is, (int64_t)cnt[1], keff, sadd, h->stream));
-            double *mass_out = h->red.as<double>() + 40;
-            HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, mass_out, m,
+            h->select_tmp.ensure(select_scratch_bytes(cap));
+            HIP_TRY(launch_select(kf, hf, if_, (int64_t)cnt[0], keff, srem, h->select_tmp.p, cap,
+                                  h->stream));
+            HIP_TRY(launch_select(ks, hs, is, (int64_t)cnt[1], keff, sadd, h->select_tmp.p, cap,
+                                  h->stream));
+            h->removed_rho.ensure((size_t)keff * sizeof(double));
+            double *rrho = h->removed_rho.as<double>();
+            HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, rrho, m,
                                 h->stream));
             if (p->reinit == LBM_WARM) {
                 with_storage(h->precision, [&](auto t) {
@@ -1251,10 +1284,11 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
                                    hipMemcpyDeviceToHost, h->stream));
             HIP_TRY(hipMemcpyAsync(add.data(), sadd, keff * sizeof(int32_t),
                                    hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(hipMemcpyAsync(h->pinned, mass_out, sizeof(double),
+            std::vector<double> rr(keff);
+            HIP_TRY(hipMemcpyAsync(rr.data(), rrho, keff * sizeof(double),
                                    hipMemcpyDeviceToHost, h->stream));
             HIP_TRY(hipStreamSynchronize(h->stream));
-            mass_removed = h->pinned[0];
+            for (int64_t k = 0; k < keff; ++k) mass_removed += rr[k];  // selection order
         }
         if (p->reinit == LBM_COLD) {
             with_storage(h->precision, [&](auto t) { reset_all<decltype(t)>(h); });
@@ -1276,7 +1310,11 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
         }
         h->last_removed.assign(rem.begin(), rem.end());
         h->last_added.assign(add.begin(), add.end());
-        if (keff > 0) rebuild_tiles(h);
+        if (keff > 0) {
+            tilings_flip(h, rem, add);
+            rebuild_tiles(h);
+            ++h->mask_version;
+        }
         r->k_eff = (int32_t)keff;
         r->n_fluid_after = nf_after;
         r->mass_removed = mass_removed;
@@ -1588,6 +1626,40 @@ void lbm_batch_destroy(lbm_batch *b) {
     (void)hipSetDevice(b->device);
     (void)hipStreamSynchronize(b->stream);
     delete b;
+}
+
+int lbm_batch_set_graphs(lbm_batch *b, int32_t enable) {
+    g_error.clear();
+    if (!b) return fail(LBM_EINVAL, "null batch");
+    b->use_graphs = enable != 0;
+    if (!b->use_graphs) b->drop_graphs();
+    return LBM_OK;
+}
+
+int lbm_state_digest(lbm_handle *h, uint64_t *digest) {
+    g_error.clear();
+    if (!h || !digest) return fail(LBM_EINVAL, "null argument");
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        ensure_pinned(h, 64 * sizeof(double));
+        unsigned long long *acc = h->red.as<unsigned long long>() + 52;
+        HIP_TRY(hipMemsetAsync(acc, 0, sizeof(unsigned long long), h->stream));
+        with_storage(h->precision, [&](auto t) {
+            using T = decltype(t);
+            HIP_TRY(launch_digest<T>(h->f[h->cur].as<T>(), h->cell.as<uint16_t>(),
+                                     h->types.as<uint8_t>(), h->nx, h->ny, h->pitch, h->plane,
+                                     acc, h->stream));
+        });
+        HIP_TRY(hipMemcpyAsync(h->pinned, acc, sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        *digest = *reinterpret_cast<const uint64_t *>(h->pinned);
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    return LBM_OK;
 }
 
 }  // extern "C"

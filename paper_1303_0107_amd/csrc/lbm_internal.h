@@ -193,12 +193,22 @@ template <typename T>
 hipError_t launch_import_plane(T *f, const uint16_t *cell, const double *in,
                                int i, int nx, int ny, int pitch, size_t plane,
                                hipStream_t s);
+// Order-free 64-bit digest of the stored state and the type map, added to *out.
+template <typename T>
+hipError_t launch_digest(const T *f, const uint16_t *cell, const uint8_t *types, int nx,
+                         int ny, int pitch, size_t plane, unsigned long long *out,
+                         hipStream_t s);
 hipError_t launch_keys(const KeysArgs &a, hipStream_t s);
-hipError_t launch_rank(const uint64_t *key, const uint64_t *hash,
-                       const int32_t *idx, int64_t count, int64_t k_eff,
-                       int32_t *sel, hipStream_t s);
+// The k_eff first of `count` candidates in the order (key, hash), written as
+// cell indices to sel.  `scratch` holds select_scratch_bytes(cap) bytes,
+// count <= cap.
+size_t select_scratch_bytes(int64_t cap);
+hipError_t launch_select(const uint64_t *key, const uint64_t *hash, const int32_t *idx,
+                         int64_t count, int64_t k_eff, int32_t *sel, void *scratch,
+                         int64_t cap, hipStream_t s);
+// Flip the selected cells; removed_rho[k] = rho[removed[k]].
 hipError_t launch_flip(uint8_t *types, const int32_t *removed,
-                       const int32_t *added, int k_eff, double *mass_out,
+                       const int32_t *added, int k_eff, double *removed_rho,
                        const double *rho, hipStream_t s);
 hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
                              unsigned long long *out, hipStream_t s);

@@ -460,48 +460,6 @@ __global__ __launch_bounds__(256) void keys_kernel(KeysArgs a) {
     }
 }
 
-__device__ __forceinline__ bool comp_less(uint64_t ka, uint64_t ha, int32_t ia,
-                                          uint64_t kb, uint64_t hb,
-                                          int32_t ib) {
-    if (ka != kb) return ka < kb;
-    if (ha != hb) return ha < hb;
-    return ia < ib;
-}
-
-// Rank of every candidate in its list (number of candidates ordered before
-// it); those with rank < k_eff are written to sel[rank].  Tiles of the list
-// are staged in LDS.  Ranks are unique because the indices are.
-__global__ __launch_bounds__(256) void rank_kernel(const uint64_t *key,
-                                                   const uint64_t *hash,
-                                                   const int32_t *idx,
-                                                   int64_t count,
-                                                   int64_t k_eff,
-                                                   int32_t *sel) {
-    __shared__ uint64_t sk[256];
-    __shared__ uint64_t sh[256];
-    __shared__ int32_t si[256];
-    const int64_t me = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool valid = me < count;
-    const uint64_t mk = valid ? key[me] : 0, mh = valid ? hash[me] : 0;
-    const int32_t mi = valid ? idx[me] : 0;
-    int64_t rank = 0;
-    for (int64_t base = 0; base < count; base += 256) {
-        const int64_t j = base + threadIdx.x;
-        if (j < count) {
-            sk[threadIdx.x] = key[j];
-            sh[threadIdx.x] = hash[j];
-            si[threadIdx.x] = idx[j];
-        }
-        __syncthreads();
-        const int lim = (int)((count - base) < 256 ? (count - base) : 256);
-        if (valid)
-            for (int t = 0; t < lim; ++t)
-                rank += comp_less(sk[t], sh[t], si[t], mk, mh, mi) ? 1 : 0;
-        __syncthreads();
-    }
-    if (valid && rank < k_eff) sel[rank] = mi;
-}
-
 // Apply the exchange to the logical type map.
 __global__ void flip_kernel(uint8_t *types, const int32_t *removed,
                             const int32_t *added, int k_eff) {
@@ -511,13 +469,11 @@ __global__ void flip_kernel(uint8_t *types, const int32_t *removed,
     types[added[k]] = kFluid;
 }
 
-// Sum of rho over the removed cells in selection order (one thread).
-__global__ void removed_mass_kernel(const double *rho, const int32_t *removed,
-                                    int k_eff, double *out) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    double s = 0.0;
-    for (int k = 0; k < k_eff; ++k) s += rho[removed[k]];
-    out[0] = s;
+// Density of each removed cell, in selection order.
+__global__ void removed_rho_kernel(const double *rho, const int32_t *removed, int k_eff,
+                                   double *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < k_eff) out[k] = rho[removed[k]];
 }
 
 __global__ __launch_bounds__(256) void count_type_kernel(const uint8_t *types,
@@ -673,21 +629,12 @@ hipError_t launch_keys(const KeysArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rank(const uint64_t *key, const uint64_t *hash,
-                       const int32_t *idx, int64_t count, int64_t k_eff,
-                       int32_t *sel, hipStream_t s) {
-    if (count <= 0 || k_eff <= 0) return hipSuccess;
-    hipLaunchKernelGGL(rank_kernel, dim3((unsigned)((count + 255) / 256)),
-                       dim3(256), 0, s, key, hash, idx, count, k_eff, sel);
-    return hipGetLastError();
-}
-
 hipError_t launch_flip(uint8_t *types, const int32_t *removed,
-                       const int32_t *added, int k_eff, double *mass_out,
+                       const int32_t *added, int k_eff, double *removed_rho,
                        const double *rho, hipStream_t s) {
     if (k_eff <= 0) return hipSuccess;
-    hipLaunchKernelGGL(removed_mass_kernel, dim3(1), dim3(64), 0, s, rho,
-                       removed, k_eff, mass_out);
+    hipLaunchKernelGGL(removed_rho_kernel, dim3((k_eff + 255) / 256), dim3(256), 0, s, rho,
+                       removed, k_eff, removed_rho);
     hipLaunchKernelGGL(flip_kernel, dim3((k_eff + 255) / 256), dim3(256), 0, s,
                        types, removed, added, k_eff);
     return hipGetLastError();
@@ -702,6 +649,60 @@ hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
                        s, types, count, which, out);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// State digest: sum mod 2^64 over cells of SplitMix64 of each stored
+// population's bits mixed with its logical position, plus each cell's type.
+template <typename T>
+__device__ __forceinline__ uint64_t raw_bits(T v) {
+    uint64_t r = 0;
+    __builtin_memcpy(&r, &v, sizeof(T));
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void digest_kernel(const T *f, const uint16_t *cell,
+                                                     const uint8_t *types, int nx, int ny,
+                                                     int pitch, size_t plane,
+                                                     unsigned long long *out) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    uint64_t acc = 0;
+    if (x < nx && y < ny) {
+        const size_t n = (size_t)y * pitch + x;
+        const uint64_t l = (uint64_t)y * (uint64_t)nx + (uint64_t)x;
+        const uint8_t t = types[l];
+        acc += splitmix64((uint64_t)t ^ (l << 8) ^ 0xd1b54a32d192ed03ull);
+        if ((cell[n] >> 8) != kSolid) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                acc += splitmix64(raw_bits(f[(size_t)i * plane + n]) ^
+                                  ((9 * l + (uint64_t)i) * 0x9e3779b97f4a7c15ull));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0 && acc != 0) atomicAdd(out, (unsigned long long)acc);
+}
+
+template <typename T>
+hipError_t launch_digest(const T *f, const uint16_t *cell, const uint8_t *types, int nx,
+                         int ny, int pitch, size_t plane, unsigned long long *out,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(digest_kernel<T>, grid_cells(nx, ny), dim3(64, 4), 0, s, f, cell, types,
+                       nx, ny, pitch, plane, out);
+    return hipGetLastError();
+}
+template hipError_t launch_digest<double>(const double *, const uint16_t *, const uint8_t *,
+                                          int, int, int, size_t, unsigned long long *,
+                                          hipStream_t);
+template hipError_t launch_digest<float>(const float *, const uint16_t *, const uint8_t *,
+                                         int, int, int, size_t, unsigned long long *,
+                                         hipStream_t);
+template hipError_t launch_digest<h16>(const h16 *, const uint16_t *, const uint8_t *, int,
+                                       int, int, size_t, unsigned long long *, hipStream_t);
+template hipError_t launch_digest<bf16>(const bf16 *, const uint16_t *, const uint8_t *, int,
+                                        int, int, size_t, unsigned long long *, hipStream_t);
 
 // Offset-storage instantiations (double precision: lbm_f64.hip).
 #define LBM_OFFSET_INST(T)                                                                  \

@@ -22,6 +22,7 @@ outlets, channel widths shrinking per generation) at lattice resolution:
 """
 from __future__ import annotations
 
+import dataclasses
 import math
 from dataclasses import dataclass, field
 
@@ -218,6 +219,60 @@ def batch_candidates(count: int = 256, seed: int = 4):
         except ValueError:
             continue
         out.append(Workload(f"cand{len(out)}", nx, ny, L, ws, tau, up, seed=seed))
+    return out
+
+
+@dataclasses.dataclass
+class ServeRequest:
+    """One request of the serving workload: arrival time (s), lattice, storage
+    form ("f32" or "f16"), kind ("solve" or "optimize") and step counts."""
+    t: float
+    workload: Workload
+    storage: str
+    kind: str
+    solve_steps: int
+    iterations: int
+    steps_per_iteration: int
+    seed: int
+
+
+def serving_requests(rate: float = 50.0, seconds: float = 60.0, seed: int = 5,
+                     solve_steps: int = 500, opt_warm: int = 100, opt_iters: int = 20,
+                     opt_steps: int = 40):
+    """Poisson arrivals (rate per second) over `seconds`.  Lattices:
+    nx = 64 round(256 2^U(0,4) / 64) (256..4096), ny = nx/2; levels, widths,
+    tau and u_peak drawn as in batch_candidates.  Storage FP32 / FP16 offsets
+    and solve / optimize each with probability 1/2.  solve: solve_steps steps
+    from rest; optimize: opt_warm steps, then opt_iters x (exchange step +
+    opt_steps steps)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= seconds:
+            break
+        while True:
+            nx = int(64 * round(256 * 2.0 ** rng.uniform(0.0, 4.0) / 64))
+            ny = nx // 2
+            L = int(rng.integers(2, 5))
+            ws = [max(2, int(round(ny / 8 * 2.0 ** (-k) * rng.uniform(0.75, 1.25))))
+                  for k in range(L + 1)]
+            tau = float(rng.uniform(0.55, 1.0))
+            up = float(rng.uniform(0.02, 0.06))
+            try:
+                check_widths(ny, L, ws)
+                break
+            except ValueError:
+                continue
+        storage = "f32" if rng.random() < 0.5 else "f16"
+        kind = "solve" if rng.random() < 0.5 else "optimize"
+        w = Workload(f"req{len(out)}", nx, ny, L, ws, tau, up, seed=seed)
+        if kind == "solve":
+            out.append(ServeRequest(t, w, storage, kind, solve_steps, 0, 0, len(out)))
+        else:
+            out.append(ServeRequest(t, w, storage, kind, opt_warm, opt_iters, opt_steps,
+                                    len(out)))
     return out
 
 

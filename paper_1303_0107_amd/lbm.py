@@ -25,6 +25,7 @@ LBM_SOLID, LBM_FLUID, LBM_INLET, LBM_OUTLET = 0, 1, 2, 3
 LBM_F64, LBM_F32, LBM_F32_S_F16, LBM_F32_S_BF16 = 0, 1, 2, 3
 LBM_WARM, LBM_COLD = 0, 1
 LBM_CRIT_PAPER, LBM_CRIT_SPEED = 0, 1
+LBM_REQ_SOLVE, LBM_REQ_OPTIMIZE = 0, 1
 
 
 class LbmError(RuntimeError):
@@ -60,6 +61,36 @@ class lbm_shape_result(ctypes.Structure):
                 ("n_cand_fluid", ctypes.c_int64), ("n_cand_solid", ctypes.c_int64),
                 ("n_fluid_before", ctypes.c_int64), ("n_fluid_after", ctypes.c_int64),
                 ("mass_removed", ctypes.c_double), ("mass_added", ctypes.c_double)]
+
+
+class lbm_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_sessions", ctypes.c_int32),
+                ("quantum", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
+
+
+class lbm_request(ctypes.Structure):
+    _fields_ = [("geom", lbm_geometry_desc), ("kind", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("solve_steps", ctypes.c_int64),
+                ("steps_per_iteration", ctypes.c_int64), ("shape", lbm_shape_params)]
+
+
+class lbm_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("iterations_done", ctypes.c_int32), ("steps", ctypes.c_int64),
+                ("cells", ctypes.c_int64), ("digest", ctypes.c_uint64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("stats", lbm_stats)]
+
+
+class lbm_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("active", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("cell_steps", ctypes.c_int64), ("nonsolid_cell_steps", ctypes.c_int64),
+                ("busy_seconds", ctypes.c_double), ("admit_seconds", ctypes.c_double),
+                ("sweep_seconds", ctypes.c_double), ("event_seconds", ctypes.c_double),
+                ("peak_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -107,6 +138,14 @@ def load() -> ctypes.CDLL:
         "lbm_batch_tune": (ctypes.c_int, [H, i32, P, P, P, i32]),
         "lbm_batch_info": (ctypes.c_int, [H, P, P, P]),
         "lbm_batch_destroy": (None, [H]),
+        "lbm_batch_set_graphs": (ctypes.c_int, [H, i32]),
+        "lbm_state_digest": (ctypes.c_int, [H, P]),
+        "lbm_server_create": (ctypes.c_int, [P, P, ctypes.POINTER(H)]),
+        "lbm_server_submit": (ctypes.c_int, [H, P, P]),
+        "lbm_server_poll": (ctypes.c_int, [H, P, i32, i32]),
+        "lbm_server_drain": (ctypes.c_int, [H]),
+        "lbm_server_stats_get": (ctypes.c_int, [H, P]),
+        "lbm_server_destroy": (None, [H]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -328,6 +367,72 @@ def lbm_batch_destroy(b) -> None:
     load().lbm_batch_destroy(b)
 
 
+def lbm_batch_set_graphs(b, enable: bool) -> None:
+    _check(load().lbm_batch_set_graphs(b, int(bool(enable))))
+
+
+def lbm_state_digest(h) -> int:
+    d = ctypes.c_uint64(0)
+    _check(load().lbm_state_digest(h, ctypes.byref(d)))
+    return d.value
+
+
+def make_request(nx, ny, levels, widths, tau, u_peak, precision=LBM_F32, kind=LBM_REQ_SOLVE,
+                 solve_steps=500, iterations=0, steps_per_iteration=0, frac=0.01, seed=0,
+                 band_x=2, band_y=1, criterion=LBM_CRIT_PAPER, reinit=LBM_WARM, rho_out=1.0):
+    r = lbm_request()
+    r.geom = make_desc(nx, ny, tau, u_peak, rho_out, precision, levels, widths)
+    r.kind = int(kind)
+    r.iterations = int(iterations)
+    r.solve_steps = int(solve_steps)
+    r.steps_per_iteration = int(steps_per_iteration)
+    r.shape = make_shape_params(frac, seed, band_x, band_y, criterion, reinit)
+    return r
+
+
+class Server:
+    """Owning wrapper of a request server (worker thread in the library)."""
+
+    def __init__(self, hbm_budget: int, max_sessions: int = 64, quantum: int = 20,
+                 variant: int = -1, order: int = 1, stream=None):
+        cfg = lbm_server_config(int(hbm_budget), int(max_sessions), int(quantum), int(variant),
+                                int(order))
+        if stream is None:
+            stream = current_stream_handle()
+        out = ctypes.c_void_p()
+        _check(load().lbm_server_create(ctypes.byref(cfg), stream, ctypes.byref(out)))
+        self.s = out
+
+    def submit(self, req: lbm_request) -> int:
+        i = ctypes.c_uint64(0)
+        _check(load().lbm_server_submit(self.s, ctypes.byref(req), ctypes.byref(i)))
+        return i.value
+
+    def poll(self, cap: int = 256, wait_ms: int = 0):
+        arr = (lbm_result * max(cap, 1))()
+        n = _check(load().lbm_server_poll(self.s, arr, int(cap), int(wait_ms)))
+        return [arr[k] for k in range(n)]
+
+    def drain(self) -> None:
+        _check(load().lbm_server_drain(self.s))
+
+    def stats(self) -> lbm_server_stats:
+        st = lbm_server_stats()
+        _check(load().lbm_server_stats_get(self.s, ctypes.byref(st)))
+        return st
+
+    def close(self):
+        if self.s:
+            load().lbm_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Lattice:
     """Owning wrapper of one handle."""
 
@@ -390,6 +495,9 @@ class Lattice:
 
     def autotune(self, trial_steps):
         return lbm_autotune(self.h, trial_steps, lbm_tb_variant_count(self.precision))
+
+    def digest(self):
+        return lbm_state_digest(self.h)
 
 
 class Batch:

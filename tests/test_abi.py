@@ -14,6 +14,8 @@ EXPECTED = {
     "lbm_profile_sweeps", "lbm_tb_variant_count", "lbm_tb_variant_info",
     "lbm_set_tb_variant", "lbm_autotune", "lbm_batch_create", "lbm_batch_run",
     "lbm_batch_configure", "lbm_batch_tune", "lbm_batch_info", "lbm_batch_destroy",
+    "lbm_batch_set_graphs", "lbm_state_digest", "lbm_server_create", "lbm_server_submit",
+    "lbm_server_poll", "lbm_server_drain", "lbm_server_stats_get", "lbm_server_destroy",
 }
 
 
@@ -39,6 +41,10 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(lbm.lbm_geometry_desc) == 4 * 12 + 3 * 8 + 8
     assert ctypes.sizeof(lbm.lbm_stats) == 8 + 16 + 7 * 8 + 8
     assert ctypes.sizeof(lbm.lbm_shape_params) == 8 + 8 + 16
+    assert ctypes.sizeof(lbm.lbm_server_config) == 8 + 16
+    assert ctypes.sizeof(lbm.lbm_request) == ctypes.sizeof(lbm.lbm_geometry_desc) + 8 + 16 + 32
+    assert ctypes.sizeof(lbm.lbm_result) == 8 + 8 + 8 + 8 + 8 + 24 + ctypes.sizeof(lbm.lbm_stats)
+    assert ctypes.sizeof(lbm.lbm_server_stats) == 8 * 8 + 4 * 8 + 8
     assert ctypes.sizeof(lbm.lbm_shape_result) == 8 + 32 + 16
 
 

@@ -1,0 +1,158 @@
+"""The request server (continuous batching) through the C ABI.
+
+Every lattice's arithmetic is independent of the others and of how its
+steps are grouped into launches, so the bar is bit-identity: a request's
+result (outlet statistics and the digest of its final state and mask) is
+the same in a mix of concurrent requests, alone on a server, and done by
+hand with the handle calls the request stands for."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1303_0107_amd import inputs as I
+from paper_1303_0107_amd import lbm
+
+pytestmark = pytest.mark.gpu
+GiB = 1 << 30
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    lbm.load()
+
+
+def _requests(n, seed=21):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, c in enumerate(I.batch_candidates(count=n, seed=seed)):
+        prec = lbm.LBM_F32 if k % 2 == 0 else lbm.LBM_F32_S_F16
+        if k % 3 == 0:
+            r = lbm.make_request(c.nx, c.ny, c.levels, c.widths, c.tau, c.u_peak, prec,
+                                 lbm.LBM_REQ_SOLVE, solve_steps=int(rng.integers(30, 130)))
+        else:
+            r = lbm.make_request(c.nx, c.ny, c.levels, c.widths, c.tau, c.u_peak, prec,
+                                 lbm.LBM_REQ_OPTIMIZE, solve_steps=int(rng.integers(20, 90)),
+                                 iterations=int(rng.integers(1, 4)),
+                                 steps_per_iteration=int(rng.integers(10, 50)),
+                                 frac=0.02, seed=100 + k)
+        out.append(r)
+    return out
+
+
+def _by_hand(r):
+    """The handle calls a request stands for."""
+    g = r.geom
+    lat = lbm.Lattice(None, g.tau, g.u_peak, g.rho_out, g.precision, g.nx, g.ny, g.levels,
+                      list(g.widths)[:g.levels + 1])
+    if r.solve_steps:
+        lat.run(r.solve_steps, 0.0, r.solve_steps)
+    if r.kind == lbm.LBM_REQ_OPTIMIZE:
+        for it in range(r.iterations):
+            p = r.shape
+            lat.shape_update(p.frac, p.seed + it, p.band_x, p.band_y, p.criterion, p.reinit)
+            if r.steps_per_iteration:
+                lat.run(r.steps_per_iteration, 0.0, r.steps_per_iteration)
+    flow, st = lat.stats()
+    d = lat.digest()
+    lat.close()
+    return d, st
+
+
+def _run(server, reqs, stagger=None):
+    ids = []
+    for k, r in enumerate(reqs):
+        ids.append(server.submit(r))
+        if stagger and k % stagger == stagger - 1:
+            time.sleep(0.02)
+    server.drain()
+    res = {x.id: x for x in server.poll(cap=len(reqs) + 8)}
+    return [res[i] for i in ids]
+
+
+def _same(a, b):
+    assert a.status == b.status == lbm.LBM_OK
+    assert a.digest == b.digest
+    assert a.steps == b.steps and a.iterations_done == b.iterations_done
+    for f in ("dp", "theta", "dg", "flow_in", "mass", "flow_ave"):
+        x, y = getattr(a.stats, f), getattr(b.stats, f)
+        assert x == y or (np.isnan(x) and np.isnan(y)), f
+
+
+def test_results_are_identical_alone_and_in_the_mix():
+    reqs = _requests(12)
+    srv = lbm.Server(hbm_budget=64 * GiB, max_sessions=16, quantum=20)
+    mix = _run(srv, reqs, stagger=3)
+    st = srv.stats()
+    srv.close()
+    assert st.completed == len(reqs) and st.rejected == 0 and st.rounds > 0
+    assert st.cell_steps == sum(x.steps * x.cells for x in mix)
+    for r, m in zip(reqs, mix):
+        alone_srv = lbm.Server(hbm_budget=64 * GiB, max_sessions=1, quantum=7)
+        (alone,) = _run(alone_srv, [r])
+        alone_srv.close()
+        _same(m, alone)
+        want_steps = r.solve_steps + (r.iterations * r.steps_per_iteration
+                                      if r.kind == lbm.LBM_REQ_OPTIMIZE else 0)
+        assert m.steps == want_steps
+        assert m.t_submit <= m.t_admit <= m.t_done
+
+
+def test_server_does_what_the_handle_calls_do():
+    reqs = _requests(5, seed=22)
+    srv = lbm.Server(hbm_budget=64 * GiB, max_sessions=8, quantum=16, variant=0)
+    res = _run(srv, reqs)
+    srv.close()
+    for r, m in zip(reqs, res):
+        d, st = _by_hand(r)
+        assert m.status == lbm.LBM_OK
+        assert m.digest == d
+        for f in ("dp", "theta", "dg", "mass"):
+            x, y = getattr(m.stats, f), getattr(st, f)
+            assert x == y or (np.isnan(x) and np.isnan(y)), f
+
+
+def test_admission_by_footprint():
+    reqs = _requests(8, seed=23)
+    sizes = [lbm.lbm_footprint_bytes(r.geom) for r in reqs]
+    budget = max(sizes) + min(sizes)
+    srv = lbm.Server(hbm_budget=budget, max_sessions=8, quantum=20)
+    big = lbm.make_request(2048, 1024, 3, [128, 64, 32, 16], 0.7, 0.03, lbm.LBM_F32,
+                           solve_steps=10)
+    res = _run(srv, reqs + [big])
+    st = srv.stats()
+    srv.close()
+    assert res[-1].status == lbm.LBM_ENOMEM and res[-1].steps == 0
+    assert all(x.status == lbm.LBM_OK for x in res[:-1])
+    assert 0 < st.peak_bytes <= budget
+    assert st.rejected == 1 and st.completed == len(reqs) + 1
+    # the same requests on an unconstrained server give the same bits
+    srv = lbm.Server(hbm_budget=64 * GiB, max_sessions=8, quantum=20)
+    free = _run(srv, reqs)
+    srv.close()
+    for a, b in zip(res[:-1], free):
+        _same(a, b)
+
+
+def test_invalid_requests_are_refused():
+    srv = lbm.Server(hbm_budget=GiB, max_sessions=2, quantum=10)
+    bad = lbm.make_request(256, 128, 2, [16, 8, 4], 0.7, 0.03, lbm.LBM_F32, solve_steps=10)
+    bad.kind = 7
+    with pytest.raises(lbm.LbmError):
+        srv.submit(bad)
+    bad = lbm.make_request(256, 128, 2, [16, 8, 4], 0.7, 0.03, lbm.LBM_F32, solve_steps=-1)
+    with pytest.raises(lbm.LbmError):
+        srv.submit(bad)
+    bad = lbm.make_request(256, 128, 2, [16, 8, 4], 0.4, 0.03, lbm.LBM_F32, solve_steps=10)
+    with pytest.raises(lbm.LbmError):
+        srv.submit(bad)
+    ok = lbm.make_request(256, 128, 2, [16, 8, 4], 0.7, 0.03, lbm.LBM_F32, solve_steps=0)
+    (r,) = _run(srv, [ok])
+    assert r.status == lbm.LBM_OK and r.steps == 0
+    srv.close()
+    with pytest.raises(lbm.LbmError):
+        lbm.Server(hbm_budget=0)

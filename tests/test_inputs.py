@@ -103,3 +103,23 @@ def test_batch_candidates_reproducible_and_valid():
         assert 2 <= c.levels <= 4 and 0.55 <= c.tau <= 1.0
         t = c.types()
         assert len(_runs(t[:, -1], I.OUTLET)) == 2 ** c.levels
+
+
+def test_serving_requests_follow_their_recipe():
+    reqs = I.serving_requests(rate=50.0, seconds=20.0, seed=5)
+    again = I.serving_requests(rate=50.0, seconds=20.0, seed=5)
+    assert [(r.t, r.workload.nx, r.kind) for r in reqs] == [(r.t, r.workload.nx, r.kind) for r in again]
+    assert 800 < len(reqs) < 1200                      # Poisson, mean 1000
+    t = np.array([r.t for r in reqs])
+    assert np.all(np.diff(t) > 0) and t[-1] < 20.0
+    for r in reqs:
+        w = r.workload
+        assert w.nx % 64 == 0 and 256 <= w.nx <= 4096 and w.ny == w.nx // 2
+        assert 2 <= w.levels <= 4 and len(w.widths) == w.levels + 1
+        assert 0.55 <= w.tau <= 1.0 and 0.02 <= w.u_peak <= 0.06
+        assert r.storage in ("f32", "f16") and r.kind in ("solve", "optimize")
+        steps = r.solve_steps + r.iterations * r.steps_per_iteration
+        assert steps == (500 if r.kind == "solve" else 900)
+    f32 = np.mean([r.storage == "f32" for r in reqs])
+    solve = np.mean([r.kind == "solve" for r in reqs])
+    assert 0.4 < f32 < 0.6 and 0.4 < solve < 0.6
