@@ -42,7 +42,13 @@ MEASURED_TRAFFIC_PER_STEP = {
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
-MEASURED_TRAFFIC_PER_LAUNCH = {}
+MEASURED_TRAFFIC_PER_LAUNCH = {
+    # profiles/sweep_batch_float_batch-256-candidates.txt; variant 4 = one step per launch
+    ("batch-256-candidates", "f32", 4, 0): 775.463e6,
+    ("batch-256-candidates", "f32", 4, 1): 684.535e6,
+    ("batch-256-candidates", "f32", 0, 0): 1556.365e6,
+    ("batch-256-candidates", "f32", 0, 1): 709.181e6,
+}
 
 
 def workloads():
@@ -71,16 +77,18 @@ def copy_ceiling(nbytes: int = 1 << 28):
 
 
 def cpu_baseline(types, w, seconds: float):
+    """The oracle from rest on the same lattice, in chunks of 100 steps
+    (residual check each) until `seconds` of wall time have passed."""
     import oracle
     lat = oracle.Lattice(types, w.tau, w.u_peak)
+    steps = 0
     t0 = time.perf_counter()
-    lat.run(50, 0.0, 50)
-    dt = time.perf_counter() - t0
-    steps = max(10, int(seconds / max(dt / 50, 1e-9)))
-    lat = oracle.Lattice(types, w.tau, w.u_peak)
-    t0 = time.perf_counter()
-    lat.run(steps, 0.0, 100)
-    dt = time.perf_counter() - t0
+    while True:
+        lat.run(100, 0.0, 100)
+        steps += 100
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
     return {"value": types.size * steps / dt / 1e6, "unit": "MLUPS",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{steps} FP64 time steps of the {w.name} lattice from rest "

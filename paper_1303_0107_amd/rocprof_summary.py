@@ -13,6 +13,19 @@ import collections
 import csv
 
 
+SHORT = [("lbm::OffsetCell<float, double, double>", "F32Cell"),
+         ("lbm::OffsetCell<_Float16, float, float>", "H16Cell"),
+         ("lbm::OffsetCell<__hip_bfloat16, float, float>", "BF16Cell"),
+         ("lbm::f64::Cell", "F64Cell"), ("void ", ""), ("lbm::sweep::", ""), ("lbm::", "")]
+
+
+def short(name: str) -> str:
+    """Kernel name with the cell policy abbreviated and the argument list cut."""
+    for a, b in SHORT:
+        name = name.replace(a, b)
+    return name.split("(")[0]
+
+
 def per_kernel(path, counter):
     """Mean counter value per (kernel, grid size), dispatch counts, and the
     largest single value read by the plain copy kernel."""
@@ -41,9 +54,9 @@ def main():
     a = ap.parse_args()
     print(f"command: {a.cmd}")
     print()
-    print(f"{'kernel':70s} {'calls':>8s} {'avg_us':>9s} {'total_ms':>10s} {'pct':>6s}")
+    print(f"{'kernel':72s} {'calls':>8s} {'avg_us':>9s} {'total_ms':>10s} {'pct':>6s}")
     for r in csv.DictReader(open(a.stats)):
-        print(f"{r['Name'][:70]:70s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.3f} "
+        print(f"{short(r['Name'])[:72]:72s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.3f} "
               f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}")
     if not a.fetch:
         return
@@ -62,7 +75,7 @@ def main():
         if a.kernel in k:
             w = write.get((k, g), 0.0)
             fb, wb = v * kib * sf, w * kib * sw
-            line = (f"{k[:70]} grid {g}: dispatches {nf[(k, g)]}, fetch {fb / 1e6:.3f} MB, "
+            line = (f"{short(k)[:72]} grid {g}: dispatches {nf[(k, g)]}, fetch {fb / 1e6:.3f} MB, "
                     f"write {wb / 1e6:.3f} MB, traffic {(fb + wb) / 1e6:.3f} MB per dispatch")
             if a.algo_bytes:
                 line += f" ({(fb + wb) / a.algo_bytes:.3f} x algorithmic {a.algo_bytes / 1e6:.3f} MB)"
