@@ -13,6 +13,8 @@ Function map (paper passages):
   outlet_stats ................ Eq. 4, Eqs. 9-11
   shape_update ................ Sec. 2.2 (Eqs. 5, 6), Sec. 2.3 step (3)
   tau_from_nu ................. Sec. 2.1 (tau = 3 nu + dt/2)
+  flags NEUMANN_OUTLET, SYMMETRY_TOP ... Sec. 3.3 (the paper's own runs:
+                                zero-gradient outlet, half domain)
 """
 from __future__ import annotations
 
@@ -31,6 +33,7 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EUNSTABLE = 0, 1, -1, -2, -4
 SOLID, FLUID, INLET, OUTLET = 0, 1, 2, 3
 CRIT_PAPER, CRIT_SPEED = 0, 1
 WARM, COLD = 0, 1
+NEUMANN_OUTLET, SYMMETRY_TOP = 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -61,10 +64,13 @@ def _load():
         lib.orc_tau_from_nu.argtypes = [f64]
         lib.orc_tau_from_nu.restype = f64
         lib.orc_inlet_profile.argtypes = [i32, i32, P, f64, P]
+        lib.orc_inlet_profile_ex.argtypes = [i32, i32, P, f64, ctypes.c_int32, P]
         lib.orc_macro.argtypes = [i32, i32, P, P, P, P, P]
         lib.orc_init.argtypes = [i32, i32, P, P]
         lib.orc_run.argtypes = [i32, i32, P, f64, f64, f64, P, i64, f64, ctypes.c_int32,
                                 ctypes.c_int32, P, P]
+        lib.orc_run_ex.argtypes = [i32, i32, P, f64, f64, f64, ctypes.c_int32, P, i64, f64,
+                                   ctypes.c_int32, ctypes.c_int32, P, P]
         lib.orc_outlet_stats.argtypes = [i32, i32, P, P, P, i32, P, P, P, P, P]
         lib.orc_splitmix64.argtypes = [u64]
         lib.orc_splitmix64.restype = u64
@@ -115,11 +121,11 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
-def inlet_profile(types: np.ndarray, u_peak: float) -> np.ndarray:
+def inlet_profile(types: np.ndarray, u_peak: float, flags: int = 0) -> np.ndarray:
     t = np.ascontiguousarray(types, np.uint8)
     ny, nx = t.shape
     out = np.zeros(ny, np.float64)
-    _load().orc_inlet_profile(nx, ny, _ptr(t), float(u_peak), _ptr(out))
+    _load().orc_inlet_profile_ex(nx, ny, _ptr(t), float(u_peak), int(flags), _ptr(out))
     return out
 
 
@@ -148,10 +154,12 @@ class Lattice:
     """One lattice: cell types (ny, nx) uint8 and the post-collision state
     fs (9, ny, nx) float64."""
 
-    def __init__(self, types: np.ndarray, tau: float, u_peak: float, rho_out: float = 1.0):
+    def __init__(self, types: np.ndarray, tau: float, u_peak: float, rho_out: float = 1.0,
+                 flags: int = 0):
         self.types = np.ascontiguousarray(types, np.uint8).copy()
         self.ny, self.nx = self.types.shape
         self.tau, self.u_peak, self.rho_out = float(tau), float(u_peak), float(rho_out)
+        self.flags = int(flags)
         self.fs = np.zeros((9, self.ny, self.nx), np.float64)
         rc = _load().orc_init(self.nx, self.ny, _ptr(self.types), _ptr(self.fs))
         if rc != OK:
@@ -162,10 +170,10 @@ class Lattice:
         """Returns (status, steps_done, residual)."""
         steps = ctypes.c_int64(0)
         res = ctypes.c_double(0.0)
-        rc = _load().orc_run(self.nx, self.ny, _ptr(self.types), self.tau, self.u_peak,
-                             self.rho_out, _ptr(self.fs), int(max_steps), float(tol),
-                             int(check_every), int(bool(collide)), ctypes.byref(steps),
-                             ctypes.byref(res))
+        rc = _load().orc_run_ex(self.nx, self.ny, _ptr(self.types), self.tau, self.u_peak,
+                                self.rho_out, self.flags, _ptr(self.fs), int(max_steps),
+                                float(tol), int(check_every), int(bool(collide)),
+                                ctypes.byref(steps), ctypes.byref(res))
         if rc in (EINVAL, ENOMEM):
             raise ValueError(f"oracle run failed (rc={rc})")
         self.residual = res.value

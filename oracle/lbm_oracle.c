@@ -30,6 +30,8 @@
  *   2. boundary conditions on inlet and outlet cells (Sec. 3.3: parabolic
  *      velocity inlet; outlets at fixed density), imposed with the Zou-He
  *      non-equilibrium bounce-back construction;
+ *      or, as the paper's own runs (Sec. 3.3), a zero-gradient (Neumann)
+ *      outlet and a symmetry plane that halves the domain (flags below);
  *   3. moments rho, u (Eq. 2);
  *   4. BGK relaxation towards the second-order equilibrium (Eq. 1 and the
  *      equilibrium of Sec. 2.1).
@@ -45,6 +47,17 @@
 #define Q 9
 
 enum { T_SOLID = 0, T_FLUID = 1, T_INLET = 2, T_OUTLET = 3 };
+/* Boundary variants of Sec. 3.3 (bit flags):
+ *   ORC_NEUMANN_OUTLET  zero normal gradient of the velocity at the outlet:
+ *                       each outlet cell imposes the velocity (Eq. 2) of the
+ *                       stored state of its neighbour at x-1 (zero if that
+ *                       cell is solid) with the Zou-He velocity closure of an
+ *                       east boundary, instead of a fixed density;
+ *   ORC_SYMMETRY_TOP    the lattice is the lower half of a domain symmetric
+ *                       about the line just above row ny-1: a population
+ *                       pulled from row ny is the mirror image (c_y reversed)
+ *                       of the one leaving the cell below it in row ny-1. */
+enum { ORC_NEUMANN_OUTLET = 1, ORC_SYMMETRY_TOP = 2 };
 enum {
     ORC_OK = 0,
     ORC_NOT_CONVERGED = 1,
@@ -60,6 +73,8 @@ static const int CX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 static const int CY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 /* index of -c_i */
 static const int OPP[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+/* index of the mirror image of c_i under y -> -y */
+static const int MIRY[Q] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
 /* weights 4/9, 1/9 (i = 1..4), 1/36 (i = 5..8), Sec. 2.1 */
 static const double WT[Q] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
                              1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
@@ -116,11 +131,13 @@ double orc_tau_from_nu(double nu) { return 3.0 * nu + 0.5; }
 /* Parabolic inlet profile (Sec. 3.3) on every maximal run of inlet cells in
  * column 0: rows y0..y1, walls half a cell outside the run,
  * u(y) = 4 u_peak [(y - y0 + 1/2)(y1 + 1/2 - y)] / W^2, W = y1 - y0 + 1.
+ * With ORC_SYMMETRY_TOP a run that reaches row ny-1 is the lower half of an
+ * opening mirrored about the symmetry line: y1 = 2 ny - 1 - y0.
  * The product of the two wall distances is formed first, so rows mirrored
  * about the centre of the opening get bitwise equal values.
  * Rows that are not inlet cells get 0. */
-void orc_inlet_profile(int nx, int ny, const uint8_t *type, double u_peak,
-                       double *uin) {
+void orc_inlet_profile_ex(int nx, int ny, const uint8_t *type, double u_peak,
+                          int32_t flags, double *uin) {
     for (int y = 0; y < ny; ++y) uin[y] = 0.0;
     int y = 0;
     while (y < ny) {
@@ -130,14 +147,21 @@ void orc_inlet_profile(int nx, int ny, const uint8_t *type, double u_peak,
         }
         int y0 = y;
         while (y < ny && type[(size_t)y * nx] == T_INLET) ++y;
-        int y1 = y - 1;
+        int last = y - 1;
+        int y1 = last;
+        if ((flags & ORC_SYMMETRY_TOP) && last == ny - 1) y1 = 2 * ny - 1 - y0;
         double W = (double)(y1 - y0 + 1);
-        for (int r = y0; r <= y1; ++r) {
+        for (int r = y0; r <= last; ++r) {
             double a = (double)(r - y0) + 0.5;
             double b = (double)(y1 - r) + 0.5;
             uin[r] = 4.0 * u_peak * (a * b) / (W * W);
         }
     }
+}
+
+void orc_inlet_profile(int nx, int ny, const uint8_t *type, double u_peak,
+                       double *uin) {
+    orc_inlet_profile_ex(nx, ny, type, u_peak, 0, uin);
 }
 
 /* Input checks shared by every entry point of this file. */
@@ -156,9 +180,27 @@ static int check_types(int nx, int ny, const uint8_t *type) {
 /* Pass 1: pull streaming, Eq. 1: f_i(x) <- fs_i(x - c_i).  If x - c_i is
  * solid or outside the lattice, the link is cut by a wall halfway between the
  * two nodes, and the population that left x towards that wall, fs_opp(i)(x),
- * returns reversed (no-slip, Sec. 3.3). */
+ * returns reversed (no-slip, Sec. 3.3).  With ORC_SYMMETRY_TOP a source in
+ * row ny (just beyond the symmetry line) stands for the mirror image of row
+ * ny-1: fs_mirror(i) at (x - cx_i, ny-1) (a wall if that cell is solid or off
+ * the lattice). */
+static double pull(int nx, int ny, const uint8_t *type, const double *fs,
+                   int32_t flags, int x, int y, int i) {
+    const size_t N = (size_t)nx * ny;
+    const size_t n = (size_t)y * nx + x;
+    int sx = x - CX[i], sy = y - CY[i], pop = i;
+    if ((flags & ORC_SYMMETRY_TOP) && sy == ny) {
+        sy = ny - 1;
+        pop = MIRY[i];
+    }
+    int wall = sx < 0 || sx >= nx || sy < 0 || sy >= ny ||
+               type[(size_t)sy * nx + sx] == T_SOLID;
+    if (wall) return fs[OPP[i] * N + n];
+    return fs[pop * N + (size_t)sy * nx + sx];
+}
+
 static void stream_pass(int nx, int ny, const uint8_t *type, const double *fs,
-                        double *f) {
+                        int32_t flags, double *f) {
     const size_t N = (size_t)nx * ny;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
@@ -168,15 +210,7 @@ static void stream_pass(int nx, int ny, const uint8_t *type, const double *fs,
                 for (int i = 0; i < Q; ++i) f[i * N + n] = 0.0;
                 continue;
             }
-            for (int i = 0; i < Q; ++i) {
-                int sx = x - CX[i], sy = y - CY[i];
-                int wall = sx < 0 || sx >= nx || sy < 0 || sy >= ny ||
-                           type[(size_t)sy * nx + sx] == T_SOLID;
-                if (wall)
-                    f[i * N + n] = fs[OPP[i] * N + n];
-                else
-                    f[i * N + n] = fs[i * N + (size_t)sy * nx + sx];
-            }
+            for (int i = 0; i < Q; ++i) f[i * N + n] = pull(nx, ny, type, fs, flags, x, y, i);
         }
     }
 }
@@ -184,10 +218,13 @@ static void stream_pass(int nx, int ny, const uint8_t *type, const double *fs,
 /* Pass 2: boundary cells.
  * Inlet (x = 0): velocity (uin(y), 0) imposed; unknowns f1, f5, f8.
  * Outlet (x = nx-1): density rho_out and zero transverse velocity imposed;
- * unknowns f3, f6, f7.  The known populations (including any that came from a
- * bounce-back link at the end of an opening) are used as they are. */
-static void boundary_pass(int nx, int ny, const uint8_t *type,
-                          const double *uin, double rho_out, double *f) {
+ * unknowns f3, f6, f7.  With ORC_NEUMANN_OUTLET the outlet imposes instead
+ * the velocity (ux, uy) of the stored state fs at (nx-2, y), and its density
+ * follows from the known populations.  The known populations (including any
+ * that came from a bounce-back link at the end of an opening) are used as
+ * they are. */
+static void boundary_pass(int nx, int ny, const uint8_t *type, const double *fs,
+                          const double *uin, double rho_out, int32_t flags, double *f) {
     const size_t N = (size_t)nx * ny;
     for (int y = 0; y < ny; ++y) {
         size_t n = (size_t)y * nx;
@@ -202,9 +239,24 @@ static void boundary_pass(int nx, int ny, const uint8_t *type,
             f[8 * N + n] = f6 + 0.5 * (f2 - f4) + (1.0 / 6.0) * ru;
         }
         n = (size_t)y * nx + (nx - 1);
-        if (type[n] == T_OUTLET) {
-            double f0 = f[0 * N + n], f1 = f[1 * N + n], f2 = f[2 * N + n];
-            double f4 = f[4 * N + n], f5 = f[5 * N + n], f8 = f[8 * N + n];
+        if (type[n] != T_OUTLET) continue;
+        double f0 = f[0 * N + n], f1 = f[1 * N + n], f2 = f[2 * N + n];
+        double f4 = f[4 * N + n], f5 = f[5 * N + n], f8 = f[8 * N + n];
+        if (flags & ORC_NEUMANN_OUTLET) {
+            double ux = 0.0, uy = 0.0;
+            if (nx >= 2 && type[n - 1] != T_SOLID) {
+                double fc[Q], r, jx, jy;
+                for (int i = 0; i < Q; ++i) fc[i] = fs[i * N + n - 1];
+                moments9(fc, &r, &jx, &jy);
+                ux = jx / r;
+                uy = jy / r;
+            }
+            double rho = (f0 + f2 + f4 + 2.0 * (f1 + f5 + f8)) / (1.0 + ux);
+            double ru = rho * ux, rv = rho * uy;
+            f[3 * N + n] = f1 - (2.0 / 3.0) * ru;
+            f[7 * N + n] = f5 + 0.5 * (f2 - f4) - (1.0 / 6.0) * ru - 0.5 * rv;
+            f[6 * N + n] = f8 - 0.5 * (f2 - f4) - (1.0 / 6.0) * ru + 0.5 * rv;
+        } else {
             double ux = -1.0 + (f0 + f2 + f4 + 2.0 * (f1 + f5 + f8)) / rho_out;
             double ru = rho_out * ux;
             f[3 * N + n] = f1 - (2.0 / 3.0) * ru;
@@ -321,13 +373,14 @@ int orc_init(int nx, int ny, const uint8_t *type, double *fs) {
  * Returns ORC_OK, ORC_NOT_CONVERGED (tol > 0 not reached) or ORC_EUNSTABLE
  * (a non-finite density or velocity at a check step).
  */
-int orc_run(int nx, int ny, const uint8_t *type, double tau, double u_peak,
-            double rho_out, double *fs, int64_t max_steps, double tol,
-            int32_t check_every, int32_t collide, int64_t *steps_done,
-            double *res_out) {
+int orc_run_ex(int nx, int ny, const uint8_t *type, double tau, double u_peak,
+               double rho_out, int32_t flags, double *fs, int64_t max_steps, double tol,
+               int32_t check_every, int32_t collide, int64_t *steps_done,
+               double *res_out) {
     if (check_types(nx, ny, type) != ORC_OK) return ORC_EINVAL;
     if (!(tau > 0.5) || check_every < 1 || max_steps < 0 || !(rho_out > 0.0))
         return ORC_EINVAL;
+    if (flags & ~(ORC_NEUMANN_OUTLET | ORC_SYMMETRY_TOP)) return ORC_EINVAL;
     const size_t N = (size_t)nx * ny;
     double *f = malloc(sizeof(double) * Q * N);
     double *rho = malloc(sizeof(double) * N);
@@ -341,7 +394,7 @@ int orc_run(int nx, int ny, const uint8_t *type, double tau, double u_peak,
         status = ORC_ENOMEM;
         goto out;
     }
-    orc_inlet_profile(nx, ny, type, u_peak, uin);
+    orc_inlet_profile_ex(nx, ny, type, u_peak, flags, uin);
     moments_pass(nx, ny, type, fs, rho, pux, puy);
     int64_t done = 0;
     double res = 0.0;
@@ -349,8 +402,8 @@ int orc_run(int nx, int ny, const uint8_t *type, double tau, double u_peak,
         int64_t chunk = max_steps - done;
         if (chunk > check_every) chunk = check_every;
         for (int64_t s = 0; s < chunk; ++s) {
-            stream_pass(nx, ny, type, fs, f);
-            boundary_pass(nx, ny, type, uin, rho_out, f);
+            stream_pass(nx, ny, type, fs, flags, f);
+            boundary_pass(nx, ny, type, fs, uin, rho_out, flags, f);
             moments_pass(nx, ny, type, f, rho, ux, uy);
             if (collide)
                 collide_pass(nx, ny, type, f, rho, ux, uy, tau, fs);
@@ -380,6 +433,14 @@ out:
     free(puy);
     free(uin);
     return status;
+}
+
+int orc_run(int nx, int ny, const uint8_t *type, double tau, double u_peak,
+            double rho_out, double *fs, int64_t max_steps, double tol,
+            int32_t check_every, int32_t collide, int64_t *steps_done,
+            double *res_out) {
+    return orc_run_ex(nx, ny, type, tau, u_peak, rho_out, 0, fs, max_steps, tol,
+                      check_every, collide, steps_done, res_out);
 }
 
 /*

@@ -87,6 +87,36 @@ def distributor(nx: int, ny: int, levels: int, widths=None) -> np.ndarray:
     return _mark_ports(t)
 
 
+def collector(nx: int, ny: int, levels: int, widths=None) -> np.ndarray:
+    """The flow direction of the paper's own run (Sec. 3.3): the distributor's
+    channels mirrored left to right, so 2^levels inlets on column 0 (the
+    former outlets, equal widths, hence equal parabolic flow rates) merge into
+    one outlet on column nx-1."""
+    t = distributor(nx, ny, levels, widths)
+    fluid = (t != SOLID)[:, ::-1]
+    out = np.where(fluid, FLUID, SOLID).astype(np.uint8)
+    return _mark_ports(out)
+
+
+def t_junction(nx: int, ny: int, w_in: int, w_out: int) -> np.ndarray:
+    """Synthetic T-junction (the elemental example of Sec. 2.3, whose figure
+    is not available): an inlet stem w_in rows wide along the mid-height meets
+    a crossbar w_out columns wide at x = nx/2 at right angles; two arms w_out
+    rows wide leave its ends at y = ny/4 and 3ny/4 for the outlets on column
+    nx-1.  It is the one-level tree of the distributor generator."""
+    return distributor(nx, ny, 1, [w_in, w_out])
+
+
+def lower_half(types: np.ndarray) -> np.ndarray:
+    """Rows 0..ny/2-1 of a map that is mirror symmetric about the line
+    between rows ny/2-1 and ny/2 (checked): the computational domain of a
+    half-domain run with a symmetry plane above its top row (Sec. 3.3)."""
+    ny = types.shape[0]
+    if ny % 2 or not np.array_equal(types, types[::-1]):
+        raise ValueError("map is not mirror symmetric about its mid line")
+    return np.ascontiguousarray(types[: ny // 2])
+
+
 def channel(nx: int, ny: int) -> np.ndarray:
     """Straight channel: solid rows 0 and ny-1, inlet column 0, outlet column
     nx-1, fluid elsewhere (the all-fluid throughput workload and the
