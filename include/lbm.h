@@ -86,8 +86,24 @@ typedef struct {
     double u_peak;      /* peak of the parabolic inlet profile (lattice u)*/
     double rho_out;     /* density imposed on outlet cells, > 0           */
     int32_t precision;  /* LBM_F64, LBM_F32, LBM_F32_S_F16, LBM_F32_S_BF16 */
-    int32_t reserved;   /* must be 0                                      */
+    int32_t flags;      /* boundary variants, LBM_NEUMANN_OUTLET |
+                           LBM_SYMMETRY_TOP (0: Zou-He density outlets,
+                           full domain)                                   */
 } lbm_geometry_desc;
+
+/* Boundary variants of the paper's own runs (Sec. 3.3).
+ * LBM_NEUMANN_OUTLET: outlet cells take no density closure (rho_out is then
+ *   unused); the populations entering an outlet cell from outside (c_x < 0)
+ *   are those its neighbour at x-1 receives in the same streaming step, walls
+ *   included (zero gradient across the outlet).  An outlet cell whose x-1
+ *   neighbour is solid gets plain bounce-back there.
+ * LBM_SYMMETRY_TOP: the lattice is the lower half of a domain that is mirror
+ *   symmetric about the line just above row ny-1.  A population that would be
+ *   pulled from row ny is the mirror image (c_y reversed) of the one leaving
+ *   the cell in row ny-1 below it; an inlet opening that reaches row ny-1 is
+ *   the lower half of an opening mirrored about that line (its parabola
+ *   spans both halves). */
+enum { LBM_NEUMANN_OUTLET = 1, LBM_SYMMETRY_TOP = 2 };
 
 /* Boundary reductions of one state (Eq. 4, Eqs. 9-11). */
 typedef struct {

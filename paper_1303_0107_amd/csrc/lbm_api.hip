@@ -186,8 +186,8 @@ bool check_desc(const lbm_geometry_desc *d, std::string &why) {
         why = "unknown precision";
         return false;
     }
-    if (d->reserved != 0) {
-        why = "reserved field must be 0";
+    if (d->flags & ~(LBM_NEUMANN_OUTLET | LBM_SYMMETRY_TOP)) {
+        why = "unknown boundary flags";
         return false;
     }
     return true;
@@ -216,7 +216,7 @@ bool check_types(int nx, int ny, const uint8_t *t, std::string &why) {
 }  // namespace
 
 struct lbm_handle {
-    int nx = 0, ny = 0, pitch = 0, precision = LBM_F64, device = 0;
+    int nx = 0, ny = 0, pitch = 0, precision = LBM_F64, device = 0, flags = 0;
     size_t plane = 0;
     double tau = 1, u_peak = 0, rho_out = 1;
     hipStream_t stream = nullptr;
@@ -406,7 +406,9 @@ void rebuild_tiles(lbm_handle *h) {
 
 // Parabolic inlet profile (Sec. 3.3) on each maximal run of inlet rows,
 // walls half a cell outside the run; the product of the two wall distances
-// first, so mirrored rows get bitwise equal values.
+// first, so mirrored rows get bitwise equal values.  Under a symmetry plane
+// above the top row, a run reaching row ny-1 is the lower half of an opening
+// mirrored about that plane.
 std::vector<double> inlet_profile(const lbm_handle *h) {
     std::vector<double> u(h->ny, 0.0);
     int y = 0;
@@ -417,9 +419,11 @@ std::vector<double> inlet_profile(const lbm_handle *h) {
         }
         const int y0 = y;
         while (y < h->ny && h->host_types[(size_t)y * h->nx] == LBM_INLET) ++y;
-        const int y1 = y - 1;
+        const int last = y - 1;
+        const int y1 =
+            ((h->flags & LBM_SYMMETRY_TOP) && last == h->ny - 1) ? 2 * h->ny - 1 - y0 : last;
         const double W = (double)(y1 - y0 + 1);
-        for (int r = y0; r <= y1; ++r) {
+        for (int r = y0; r <= last; ++r) {
             const double a = (double)(r - y0) + 0.5, b = (double)(y1 - r) + 0.5;
             u[r] = 4.0 * h->u_peak * (a * b) / (W * W);
         }
@@ -454,6 +458,7 @@ SweepArgs<T> sweep_args(lbm_handle *h, bool check) {
     a.omega = 1.0 / h->tau;
     a.rho_out = h->rho_out;
     a.one_minus_rho_out = 1.0 - h->rho_out;
+    a.flags = h->flags;
     return a;
 }
 
@@ -976,6 +981,7 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         h->tau = d->tau;
         h->u_peak = d->u_peak;
         h->rho_out = d->rho_out;
+        h->flags = d->flags;
         h->stream = static_cast<hipStream_t>(hip_stream);
         const char *g = std::getenv("LBM_GRAPHS");
         h->use_graphs = !(g && g[0] == '0');
@@ -1029,7 +1035,7 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         }
         with_storage(h->precision, [&](auto t) { reset_all<decltype(t)>(h); });
         HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
-                                   h->ny, h->pitch, h->stream));
+                                   h->ny, h->pitch, h->flags, h->stream));
         rebuild_tiles(h);
         HIP_TRY(hipStreamSynchronize(h->stream));
     } catch (const std::bad_alloc &) {
@@ -1294,7 +1300,7 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
             with_storage(h->precision, [&](auto t) { reset_all<decltype(t)>(h); });
         }
         HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
-                                   h->ny, h->pitch, h->stream));
+                                   h->ny, h->pitch, h->flags, h->stream));
         unsigned long long *fc = h->red.as<unsigned long long>() + 48;
         HIP_TRY(hipMemsetAsync(fc, 0, sizeof(unsigned long long), h->stream));
         HIP_TRY(launch_count_type(h->types.as<uint8_t>(), N, (uint8_t)LBM_FLUID, fc,

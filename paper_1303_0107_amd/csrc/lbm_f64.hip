@@ -67,12 +67,21 @@ struct Cell {
     using CT = double;
     __device__ static __forceinline__ double load(double v) { return v; }
     __device__ static __forceinline__ double store(double v) { return v; }
-    __device__ static __forceinline__ void update(double (&f)[9], uint32_t type, double uin,
-                                                  const SweepArgs<double> &a, double &mass,
-                                                  double &ux, double &uy) {
+    // Velocity (Eq. 2) of a stored population set, formed as the oracle does.
+    __device__ static __forceinline__ void velocity(double (&g)[9], double &ux, double &uy) {
+        double r, mx, my;
+        moments(g, r, mx, my);
+        ux = mx / r;
+        uy = my / r;
+    }
+    // (bx, by): the inlet velocity (inlet cells) or the velocity a Neumann
+    // outlet imposes (that of its x-1 neighbour's stored state).
+    __device__ static __forceinline__ void update(double (&f)[9], uint32_t type, double bx,
+                                                  double by, const SweepArgs<double> &a,
+                                                  double &mass, double &ux, double &uy) {
         if (type == kInlet) {
-            const double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7])) / (1.0 - uin);
-            const double ru = rho * uin;
+            const double rho = (f[0] + f[2] + f[4] + 2.0 * (f[3] + f[6] + f[7])) / (1.0 - bx);
+            const double ru = rho * bx;
             f[1] = f[3] + (2.0 / 3.0) * ru;
             f[5] = f[7] - 0.5 * (f[2] - f[4]) + (1.0 / 6.0) * ru;
             f[8] = f[6] + 0.5 * (f[2] - f[4]) + (1.0 / 6.0) * ru;
@@ -83,6 +92,12 @@ struct Cell {
             f[3] = f[1] - (2.0 / 3.0) * ru;
             f[7] = f[5] + 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * ru;
             f[6] = f[8] - 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * ru;
+        } else if (type == kOutletNeumann) {
+            const double rho = (f[0] + f[2] + f[4] + 2.0 * (f[1] + f[5] + f[8])) / (1.0 + bx);
+            const double ru = rho * bx, rv = rho * by;
+            f[3] = f[1] - (2.0 / 3.0) * ru;
+            f[7] = f[5] + 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * ru - 0.5 * rv;
+            f[6] = f[8] - 0.5 * (f[2] - f[4]) - (1.0 / 6.0) * ru + 0.5 * rv;
         }
         double r, mx, my;
         moments(f, r, mx, my);
@@ -108,7 +123,7 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroArgs<double> a) {
     const size_t n = (size_t)y * a.pitch + x;
     const size_t l = (size_t)y * a.nx + x;
     double r = 0.0, ux = 0.0, uy = 0.0;
-    if ((a.cell[n] >> 8) != kSolid) {
+    if (cell_type(a.cell[n]) != kSolid) {
         double f[9], mx, my;
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = a.f[(size_t)i * a.plane + n];
@@ -134,7 +149,7 @@ __global__ __launch_bounds__(256) void mass_kernel(MacroArgs<double> a,
     double v[1] = {0.0};
     if (x < a.nx && y < a.ny) {
         const size_t n = (size_t)y * a.pitch + x;
-        if ((a.cell[n] >> 8) != kSolid) {
+        if (cell_type(a.cell[n]) != kSolid) {
             double f[9], mx, my;
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[i] = a.f[(size_t)i * a.plane + n];
@@ -174,12 +189,12 @@ __global__ void boundary_kernel(MacroArgs<double> a, const int32_t *out_y0,
         for (int y = 0; y < a.ny; ++y) {
             const size_t n0 = (size_t)y * a.pitch;
             double r, mx;
-            if ((a.cell[n0 + a.nx - 1] >> 8) == kOutlet) {
+            if (cell_type(a.cell[n0 + a.nx - 1]) == kOutlet) {
                 at(n0 + a.nx - 1, r, mx);
                 rout += r;
                 cout += 1.0;
             }
-            if ((a.cell[n0] >> 8) == kInlet) {
+            if (cell_type(a.cell[n0]) == kInlet) {
                 at(n0, r, mx);
                 fl += mx;
                 rin += r;
@@ -218,7 +233,7 @@ __global__ __launch_bounds__(256) void export_plane_kernel(
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= nx || y >= ny) return;
     const size_t n = (size_t)y * pitch + x;
-    out[(size_t)y * nx + x] = (cell[n] >> 8) == kSolid ? 0.0 : f[(size_t)i * plane + n];
+    out[(size_t)y * nx + x] = cell_type(cell[n]) == kSolid ? 0.0 : f[(size_t)i * plane + n];
 }
 
 __global__ __launch_bounds__(256) void import_plane_kernel(
@@ -228,7 +243,7 @@ __global__ __launch_bounds__(256) void import_plane_kernel(
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= nx || y >= ny) return;
     const size_t n = (size_t)y * pitch + x;
-    f[(size_t)i * plane + n] = (cell[n] >> 8) == kSolid ? weight(i) : in[(size_t)y * nx + x];
+    f[(size_t)i * plane + n] = cell_type(cell[n]) == kSolid ? weight(i) : in[(size_t)y * nx + x];
 }
 
 }  // namespace f64

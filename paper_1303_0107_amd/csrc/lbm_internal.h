@@ -12,6 +12,26 @@ namespace lbm {
 
 enum : uint32_t { kSolid = 0, kFluid = 1, kInlet = 2, kOutlet = 3 };
 enum : int { kCritPaper = 0, kCritSpeed = 1 };
+// Lattice-wide boundary variants (Sec. 3.3): a zero-gradient outlet, and a
+// symmetry plane just above the top row (the lattice is a half domain).
+enum : int { kFlagNeumannOutlet = 1, kFlagSymmetryTop = 2 };
+
+// Cell words (uint16): bits 0..7 wall flags of populations 1..8, bits 8..9
+// the type; bit 10: an outlet with the zero-gradient (Neumann) closure; bit
+// 11: the cell's pulls need the general rule (top row under a symmetry
+// plane); bit 12: the cell at x-1 is not solid (its velocity is the one a
+// Neumann outlet imposes).
+enum : uint32_t {
+    kWordNeumann = 1u << 10,
+    kWordGeneral = 1u << 11,
+    kWordLeftLive = 1u << 12
+};
+// Type code the per-cell update sees for a Neumann outlet.
+enum : uint32_t { kOutletNeumann = 4 };
+__host__ __device__ __forceinline__ uint32_t cell_type(uint32_t w) { return (w >> 8) & 3u; }
+__host__ __device__ __forceinline__ uint32_t update_type(uint32_t w) {
+    return (w & kWordNeumann) ? kOutletNeumann : cell_type(w);
+}
 
 // 16-bit storage types of the reduced-precision forms.
 using h16 = _Float16;
@@ -79,6 +99,7 @@ struct SweepArgs {
     double omega;      // 1 / tau
     double rho_out;
     double one_minus_rho_out;
+    int flags;         // kFlagNeumannOutlet | kFlagSymmetryTop
 };
 
 template <typename T>
@@ -177,7 +198,7 @@ hipError_t launch_boundary(const MacroArgs<T> &a, const int32_t *y0,
                            const int32_t *y1, int n_out, double *out,
                            hipStream_t s);
 hipError_t launch_build_cells(const uint8_t *types, uint16_t *cell, int nx,
-                              int ny, int pitch, hipStream_t s);
+                              int ny, int pitch, int flags, hipStream_t s);
 // Put the given cells (logical indices) / the whole buffer at rest
 // (f_i = w_i: offsets 0 in single precision, w_i in double precision).
 template <typename T>

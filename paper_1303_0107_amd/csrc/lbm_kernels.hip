@@ -113,14 +113,25 @@ struct OffsetCell {
         else
             return Sto<T>::from_f((float)v);
     }
-    __device__ static __forceinline__ void update(CT (&d)[9], uint32_t type, CT uin,
+    // Velocity (Eq. 2) of a stored offset set, with the update's pairing.
+    __device__ static __forceinline__ void velocity(const CT (&d)[9], CT &ux, CT &uy) {
+        const CT dr = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[8]) + (d[6] + d[7]));
+        const CT jx = (d[1] + (d[5] + d[8])) - (d[3] + (d[6] + d[7]));
+        const CT jy = (d[2] + (d[5] + d[6])) - (d[4] + (d[8] + d[7]));
+        const CT ir = CT(1) / (CT(1) + dr);
+        ux = jx * ir;
+        uy = jy * ir;
+    }
+    // (bx, by): the inlet velocity (inlet cells) or the velocity a Neumann
+    // outlet imposes (that of its x-1 neighbour's stored state).
+    __device__ static __forceinline__ void update(CT (&d)[9], uint32_t type, CT bx, CT by,
                                                   const SweepArgs<T> &a, double &mass,
                                                   double &ux_out, double &uy_out) {
 #pragma clang fp contract(on)
         if (type == kInlet) {
             const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[3] + (d[6] + d[7]));
-            const CT dr = (s + uin) / (CT(1) - uin);
-            const CT ru = (CT(1) + dr) * uin;
+            const CT dr = (s + bx) / (CT(1) - bx);
+            const CT ru = (CT(1) + dr) * bx;
             const CT h = CT(0.5) * (d[2] - d[4]);
             d[1] = d[3] + (CT(2) / CT(3)) * ru;
             d[5] = d[7] - h + (CT(1) / CT(6)) * ru;
@@ -133,6 +144,15 @@ struct OffsetCell {
             d[3] = d[1] - (CT(2) / CT(3)) * ru;
             d[7] = d[5] + h - (CT(1) / CT(6)) * ru;
             d[6] = d[8] - h - (CT(1) / CT(6)) * ru;
+        } else if (type == kOutletNeumann) {
+            // rho = (1 + s) / (1 + ux): offsets of the Zou-He velocity closure
+            const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[1] + (d[5] + d[8]));
+            const CT dr = (s - bx) / (CT(1) + bx);
+            const CT ru = (CT(1) + dr) * bx, rv = (CT(1) + dr) * by;
+            const CT h = CT(0.5) * (d[2] - d[4]);
+            d[3] = d[1] - (CT(2) / CT(3)) * ru;
+            d[7] = d[5] + h - (CT(1) / CT(6)) * ru - CT(0.5) * rv;
+            d[6] = d[8] - h - (CT(1) / CT(6)) * ru + CT(0.5) * rv;
         }
         const CT dr = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[8]) + (d[6] + d[7]));
         const CT rho = CT(1) + dr;
@@ -199,7 +219,7 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroArgs<T> a) {
     if (x >= a.nx || y >= a.ny) return;
     const size_t n = (size_t)y * a.pitch + x;
     const size_t l = (size_t)y * a.nx + x;
-    const bool solid = (a.cell[n] >> 8) == kSolid;
+    const bool solid = cell_type(a.cell[n]) == kSolid;
     double rho = 0.0, ux = 0.0, uy = 0.0;
     if (!solid) {
         double d[9];
@@ -231,7 +251,7 @@ __global__ __launch_bounds__(256) void mass_kernel(MacroArgs<T> a,
     double v[1] = {0.0};
     if (x < a.nx && y < a.ny) {
         const size_t n = (size_t)y * a.pitch + x;
-        if ((a.cell[n] >> 8) != kSolid) {
+        if (cell_type(a.cell[n]) != kSolid) {
             double d[9], dr, jx, jy;
 #pragma unroll
             for (int i = 0; i < 9; ++i) d[i] = Sto<T>::to_d(a.f[(size_t)i * a.plane + n]);
@@ -278,12 +298,12 @@ __global__ void boundary_kernel(MacroArgs<T> a, const int32_t *out_y0,
         for (int y = 0; y < a.ny; ++y) {
             const size_t n = (size_t)y * a.pitch;
             double r, j;
-            if ((a.cell[n + a.nx - 1] >> 8) == kOutlet) {
+            if (cell_type(a.cell[n + a.nx - 1]) == kOutlet) {
                 moments(n + a.nx - 1, r, j);
                 rout += r;
                 cnt_out += 1.0;
             }
-            if ((a.cell[n] >> 8) == kInlet) {
+            if (cell_type(a.cell[n]) == kInlet) {
                 moments(n, r, j);
                 fl += j;
                 rs += r;
@@ -304,7 +324,7 @@ __global__ void boundary_kernel(MacroArgs<T> a, const int32_t *out_y0,
 __global__ __launch_bounds__(256) void build_cells_kernel(const uint8_t *types,
                                                           uint16_t *cell,
                                                           int nx, int ny,
-                                                          int pitch) {
+                                                          int pitch, int flags) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= pitch || y >= ny) return;
@@ -313,13 +333,22 @@ __global__ __launch_bounds__(256) void build_cells_kernel(const uint8_t *types,
         const uint32_t t = types[(size_t)y * nx + x];
         w = t << 8;
         if (t != kSolid) {
+            const bool sym = (flags & kFlagSymmetryTop) != 0;
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                const int sx = x - kCx[i], sy = y - kCy[i];
+                // a source beyond the symmetry line is its mirror in row ny-1
+                const int sx = x - kCx[i];
+                int sy = y - kCy[i];
+                if (sym && sy == ny) sy = ny - 1;
                 const bool wall = sx < 0 || sx >= nx || sy < 0 || sy >= ny ||
                                   types[(size_t)sy * nx + sx] == kSolid;
                 w |= (wall ? 1u : 0u) << (i - 1);
             }
+            if ((flags & kFlagNeumannOutlet) && t == kOutlet) {
+                w |= kWordNeumann;
+                if (x > 0 && types[(size_t)y * nx + x - 1] != kSolid) w |= kWordLeftLive;
+            }
+            if (sym && y == ny - 1) w |= kWordGeneral;
         }
     }
     cell[(size_t)y * pitch + x] = (uint16_t)w;
@@ -355,7 +384,7 @@ __global__ __launch_bounds__(256) void export_plane_kernel(
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= nx || y >= ny) return;
     const size_t n = (size_t)y * pitch + x;
-    const bool solid = (cell[n] >> 8) == kSolid;
+    const bool solid = cell_type(cell[n]) == kSolid;
     out[(size_t)y * nx + x] =
         solid ? 0.0 : wgt<double>(i) + Sto<T>::to_d(f[(size_t)i * plane + n]);
 }
@@ -368,7 +397,7 @@ __global__ __launch_bounds__(256) void import_plane_kernel(
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= nx || y >= ny) return;
     const size_t n = (size_t)y * pitch + x;
-    const bool solid = (cell[n] >> 8) == kSolid;
+    const bool solid = cell_type(cell[n]) == kSolid;
     f[(size_t)i * plane + n] =
         Sto<T>::from_d(solid ? 0.0 : in[(size_t)y * nx + x] - wgt<double>(i));
 }
@@ -565,9 +594,9 @@ hipError_t launch_boundary(const MacroArgs<T> &a, const int32_t *y0,
 }
 
 hipError_t launch_build_cells(const uint8_t *types, uint16_t *cell, int nx,
-                              int ny, int pitch, hipStream_t s) {
+                              int ny, int pitch, int flags, hipStream_t s) {
     hipLaunchKernelGGL(build_cells_kernel, grid_cells(pitch, ny), dim3(64, 4),
-                       0, s, types, cell, nx, ny, pitch);
+                       0, s, types, cell, nx, ny, pitch, flags);
     return hipGetLastError();
 }
 
@@ -673,7 +702,7 @@ __global__ __launch_bounds__(256) void digest_kernel(const T *f, const uint16_t 
         const uint64_t l = (uint64_t)y * (uint64_t)nx + (uint64_t)x;
         const uint8_t t = types[l];
         acc += splitmix64((uint64_t)t ^ (l << 8) ^ 0xd1b54a32d192ed03ull);
-        if ((cell[n] >> 8) != kSolid) {
+        if (cell_type(cell[n]) != kSolid) {
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 acc += splitmix64(raw_bits(f[(size_t)i * plane + n]) ^

@@ -3,7 +3,7 @@
 // A `Cell` policy supplies the storage type T, the arithmetic type CT, the
 // conversions Cell::load (T -> CT) and Cell::store (CT -> T), and the update
 // of one cell:
-//     Cell::update(CT (&f)[9], type, uin, args, mass, ux, uy)
+//     Cell::update(CT (&f)[9], type, bx, by, args, mass, ux, uy)
 // turns the nine pulled populations (after streaming, before the boundary
 // closure) into the post-collision populations, and reports the cell's
 // density and velocity.  Two kernels share it, so both produce the same bits:
@@ -39,6 +39,25 @@ namespace sweep {
 __device__ constexpr int kCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __device__ constexpr int kCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 __device__ constexpr int kOpp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+// mirror image of c_i under y -> -y
+__device__ constexpr int kMirY[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};
+
+// Pull source of population i for a cell flagged kWordGeneral (top row under
+// a symmetry plane), as an offset (plane, row, column) into an array of row
+// stride `stride`: a source beyond the symmetry line above row ny-1 is the
+// mirror population (c_y reversed) of the cell in row ny-1 (gy is the cell's
+// lattice row, ry its array row).
+__device__ __forceinline__ size_t general_src(uint32_t cw, int i, int col, int ry, int gy,
+                                              int ny, int flags, size_t plane, int stride) {
+    const bool wall = i > 0 && ((cw >> (i - 1)) & 1u);
+    if (wall) return (size_t)kOpp[i] * plane + (size_t)ry * stride + col;
+    int rs = ry - kCy[i], pop = i;
+    if ((flags & kFlagSymmetryTop) && gy - kCy[i] == ny) {
+        rs = ry;
+        pop = kMirY[i];
+    }
+    return (size_t)pop * plane + (size_t)rs * stride + (col - kCx[i]);
+}
 
 // Sum of NV doubles over a block of NT threads into thread 0, in a fixed
 // order (wave butterflies, then waves in index order).
@@ -90,20 +109,34 @@ __device__ __forceinline__ void step_body(const SweepArgs<typename Cell::T> &a, 
     const bool in = x < a.nx && y < a.ny;
     const size_t n = (size_t)(in ? y : 0) * a.pitch + (in ? x : 0);
     const uint32_t cw = in ? a.cell[n] : 0u;
-    const uint32_t type = cw >> 8;
+    const uint32_t type = update_type(cw);
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     if (in && type != kSolid) {
         const size_t P = a.plane;
-        CT f[9];
+        // boundary velocity: the inlet profile, or a Neumann outlet's neighbour
+        CT bx = type == kInlet ? (CT)a.uin[y] : CT(0), by = CT(0);
+        if (type == kOutletNeumann && (cw & kWordLeftLive)) {
+            CT g[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const bool wall = i > 0 && ((cw >> (i - 1)) & 1u);
-            const size_t src = wall ? (size_t)kOpp[i] * P + n
-                                    : (size_t)i * P + n - kCx[i] - (ptrdiff_t)kCy[i] * a.pitch;
-            f[i] = Cell::load(a.fin[src]);
+            for (int i = 0; i < 9; ++i) g[i] = Cell::load(a.fin[(size_t)i * P + n - 1]);
+            Cell::velocity(g, bx, by);
+        }
+        CT f[9];
+        if (cw & kWordGeneral) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[i] = Cell::load(a.fin[general_src(cw, i, x, y, y, a.ny, a.flags, P, a.pitch)]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const bool wall = i > 0 && ((cw >> (i - 1)) & 1u);
+                const size_t src = wall ? (size_t)kOpp[i] * P + n
+                                        : (size_t)i * P + n - kCx[i] - (ptrdiff_t)kCy[i] * a.pitch;
+                f[i] = Cell::load(a.fin[src]);
+            }
         }
         double mass, ux, uy;
-        Cell::update(f, type, type == kInlet ? (CT)a.uin[y] : CT(0), a, mass, ux, uy);
+        Cell::update(f, type, bx, by, a, mass, ux, uy);
 #pragma unroll
         for (int i = 0; i < 9; ++i) a.fout[(size_t)i * P + n] = Cell::store(f[i]);
         if (CHECK) check_terms(a, n, mass, ux, uy, part);
@@ -168,7 +201,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
         const bool in = col_in && gy >= 0 && gy < a.ny;
         const size_t n = in ? (size_t)gy * a.pitch + gx : 0;
         cw[c] = in ? a.cell[n] : 0u;
-        const bool live = in && (cw[c] >> 8) != kSolid;
+        const bool live = in && cell_type(cw[c]) != kSolid;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             L[i * PL + ry * RW + lane] = live ? a.fin[(size_t)i * a.plane + n] : Cell::store(CT(0));
@@ -186,22 +219,36 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int ry = wave + c * NW;
-            const uint32_t type = cw[c] >> 8;
+            const uint32_t type = update_type(cw[c]);
             bool v = type != kSolid && lane >= s && lane < RW - s && ry >= s && ry < RH - s;
             if (last) v = v && lane >= H && lane < H + IW && ry >= H && ry < H + IH;
             upd[c] = v;
             if (v) {
-                CT f[9];
+                const int gy = oy + ry;
+                CT bx = type == kInlet ? (CT)a.uin[gy] : CT(0), by = CT(0);
+                if (type == kOutletNeumann && (cw[c] & kWordLeftLive)) {
+                    CT g[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const bool wall = i > 0 && ((cw[c] >> (i - 1)) & 1u);
-                    const int src = wall ? kOpp[i] * PL + ry * RW + lane
-                                         : i * PL + (ry - kCy[i]) * RW + lane - kCx[i];
-                    f[i] = Cell::load(Ls[src]);
+                    for (int i = 0; i < 9; ++i) g[i] = Cell::load(Ls[i * PL + ry * RW + lane - 1]);
+                    Cell::velocity(g, bx, by);
+                }
+                CT f[9];
+                if (cw[c] & kWordGeneral) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        f[i] = Cell::load(Ls[general_src(cw[c], i, lane, ry, gy, a.ny, a.flags,
+                                                         PL, RW)]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const bool wall = i > 0 && ((cw[c] >> (i - 1)) & 1u);
+                        const int src = wall ? kOpp[i] * PL + ry * RW + lane
+                                             : i * PL + (ry - kCy[i]) * RW + lane - kCx[i];
+                        f[i] = Cell::load(Ls[src]);
+                    }
                 }
                 double mass, ux, uy;
-                const int gy = oy + ry;
-                Cell::update(f, type, type == kInlet ? (CT)a.uin[gy] : CT(0), a, mass, ux, uy);
+                Cell::update(f, type, bx, by, a, mass, ux, uy);
                 if (last) {
                     const size_t n = (size_t)gy * a.pitch + gx;
 #pragma unroll
@@ -280,7 +327,7 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
         const bool in = col_in && gy >= 0 && gy < a.ny;
         const size_t n = in ? (size_t)gy * a.pitch + gx : 0;
         cw[c] = in ? a.cell[n] : 0u;
-        const bool live = in && (cw[c] >> 8) != kSolid;
+        const bool live = in && cell_type(cw[c]) != kSolid;
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             L[i * PL + ry * RW + lane] = live ? a.fin[(size_t)i * a.plane + n] : Cell::store(CT(0));
@@ -349,17 +396,30 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
                 const uint32_t c = e >> 16;
                 const int pos = (int)(e & 0xffffu);
                 const int ry = pos / RW, lx = pos % RW;
-                const uint32_t type = c >> 8;
-                CT f[9];
+                const uint32_t type = update_type(c);
+                const int gy = oy + ry;
+                CT bx = type == kInlet ? (CT)a.uin[gy] : CT(0), by = CT(0);
+                if (type == kOutletNeumann && (c & kWordLeftLive)) {
+                    CT g[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const bool wall = i > 0 && ((c >> (i - 1)) & 1u);
-                    const int src = wall ? kOpp[i] * PL + pos : i * PL + pos - kCy[i] * RW - kCx[i];
-                    f[i] = Cell::load(Ls[src]);
+                    for (int i = 0; i < 9; ++i) g[i] = Cell::load(Ls[i * PL + pos - 1]);
+                    Cell::velocity(g, bx, by);
+                }
+                CT f[9];
+                if (c & kWordGeneral) {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i)
+                        f[i] = Cell::load(Ls[general_src(c, i, lx, ry, gy, a.ny, a.flags, PL, RW)]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 9; ++i) {
+                        const bool wall = i > 0 && ((c >> (i - 1)) & 1u);
+                        const int src = wall ? kOpp[i] * PL + pos : i * PL + pos - kCy[i] * RW - kCx[i];
+                        f[i] = Cell::load(Ls[src]);
+                    }
                 }
                 double mass, ux, uy;
-                const int gy = oy + ry;
-                Cell::update(f, type, type == kInlet ? (CT)a.uin[gy] : CT(0), a, mass, ux, uy);
+                Cell::update(f, type, bx, by, a, mass, ux, uy);
                 if (last) {
                     const size_t n = (size_t)gy * a.pitch + (ox + lx);
 #pragma unroll

@@ -26,6 +26,7 @@ LBM_F64, LBM_F32, LBM_F32_S_F16, LBM_F32_S_BF16 = 0, 1, 2, 3
 LBM_WARM, LBM_COLD = 0, 1
 LBM_CRIT_PAPER, LBM_CRIT_SPEED = 0, 1
 LBM_REQ_SOLVE, LBM_REQ_OPTIMIZE = 0, 1
+LBM_NEUMANN_OUTLET, LBM_SYMMETRY_TOP = 1, 2
 
 
 class LbmError(RuntimeError):
@@ -38,7 +39,7 @@ class lbm_geometry_desc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("widths", ctypes.c_int32 * 9), ("tau", ctypes.c_double),
                 ("u_peak", ctypes.c_double), ("rho_out", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class lbm_stats(ctypes.Structure):
@@ -173,14 +174,15 @@ def current_stream_handle():
     return torch.cuda.current_stream().cuda_stream
 
 
-def make_desc(nx, ny, tau, u_peak, rho_out=1.0, precision=LBM_F64, levels=0, widths=None):
+def make_desc(nx, ny, tau, u_peak, rho_out=1.0, precision=LBM_F64, levels=0, widths=None,
+              flags=0):
     d = lbm_geometry_desc()
     d.nx, d.ny, d.levels = int(nx), int(ny), int(levels)
     for k, w in enumerate(widths or []):
         d.widths[k] = int(w)
     d.tau, d.u_peak, d.rho_out = float(tau), float(u_peak), float(rho_out)
     d.precision = int(precision)
-    d.reserved = 0
+    d.flags = int(flags)
     return d
 
 
@@ -438,12 +440,13 @@ class Lattice:
 
     def __init__(self, types: np.ndarray | None, tau: float, u_peak: float, rho_out: float = 1.0,
                  precision: int = LBM_F64, nx: int | None = None, ny: int | None = None,
-                 levels: int = 0, widths=None, stream=None):
+                 levels: int = 0, widths=None, stream=None, flags: int = 0):
         if types is not None:
             ny, nx = types.shape
         self.nx, self.ny = int(nx), int(ny)
         self.precision = int(precision)
-        self.desc = make_desc(self.nx, self.ny, tau, u_peak, rho_out, precision, levels, widths)
+        self.desc = make_desc(self.nx, self.ny, tau, u_peak, rho_out, precision, levels, widths,
+                              flags)
         if stream is None:
             stream = current_stream_handle()
         self.h = lbm_create_geometry(self.desc, types, stream)
