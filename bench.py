@@ -35,10 +35,11 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per time step of the plain sweep launches, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size) of this
 # build's kernels; profiles/sweep_tb_float_distributor-1024x512.txt.  Keyed by
-# (workload, storage precision, kernel); reported as null for anything else
-# and must be re-measured whenever the kernel changes.
+# (workload, storage precision, region shape); reported as null for anything
+# else and must be re-measured whenever the kernel changes.
 MEASURED_TRAFFIC_PER_STEP = {
-    ("distributor-1024x512-L3", "f32", "tb_kernel"): 14.902e6 / 8,
+    # shape 0 (32x64 compacted regions, 8 steps per launch), 234 active tiles
+    ("distributor-1024x512-L3", "f32", 0): 14.949e6 / 8,
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
@@ -393,6 +394,10 @@ def main() -> int:
     rc, settle_steps, res = lat.run(settle_cap, args.tol, k)
     print(f"# settle: rc={rc} steps={settle_steps} r={res:.3e} "
           f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    shape, tune_ms = lat.autotune(max(args.tune_steps, 800))
+    rows, halo, tw, th = lbm.lbm_tb_variant_info(prec, shape)
+    print(f"# autotune: shape {shape} ({rows} rows, halo {halo}); us/step "
+          + " ".join(f"{x * 1e3:.3f}" for x in tune_ms), file=sys.stderr, flush=True)
 
     def one_step(seed):
         r, _, _ = lat.shape_update(frac=frac, seed=seed)
@@ -426,7 +431,7 @@ def main() -> int:
     n, res, flow, st, r = last
     spread = float((flow.max() - flow.min()) / flow.mean()) if len(flow) else 0.0
     kernel = "tb_kernel" if steps_per_launch > 1.0 else "step_kernel"
-    per_step = MEASURED_TRAFFIC_PER_STEP.get((w.name, args.precision, kernel))
+    per_step = MEASURED_TRAFFIC_PER_STEP.get((w.name, args.precision, shape))
     traffic = round(per_step * steps_per_launch) if per_step else None
     out = {
         "metric": METRIC,
@@ -449,11 +454,14 @@ def main() -> int:
             "sweeps_timed": sweeps, "mflups": round(nns * sweeps / wall / 1e6, 2),
             "last_dp": st.dp, "last_theta": st.theta, "last_dg": st.dg,
             "last_spread": spread, "last_residual": res,
+            "tuned_shape": {"index": shape, "rows": rows, "halo": halo, "tile": [tw, th]},
+            "tune_us_per_step": [round(x * 1e3, 3) for x in tune_ms],
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kernel + f" ({args.precision} storage)",
+            "kernel": kernel + f" ({args.precision} storage, shape {shape}: {rows}x64 region, "
+                               f"{halo} steps per launch)",
             "bytes_per_step": bytes_per_step, "steps_per_launch": round(steps_per_launch, 3),
             "bytes_per_launch": round(bytes_per_launch), "launches": launches,
             "avg_launch_us": round(avg_ms * 1e3, 3),

@@ -775,6 +775,7 @@ struct lbm_batch {
     int64_t n_items = 0;     // launch grid
     int64_t n_real = 0;      // real tiles
     bool dirty = true;
+    bool bc = false;         // some member has boundary-variant flags
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
     // Replayable runs of an even number of launches, starting at parity 0.
@@ -864,9 +865,9 @@ hipError_t batch_launch(lbm_batch *b, int parity, int steps, hipStream_t s) {
     const SweepArgs<T> *A = b->args.as<SweepArgs<T>>() + (size_t)parity * b->hs.size();
     if (batch_single_step(b))
         return launch_step_batch<T>(A, b->lat.as<int32_t>(), b->tiles.as<int32_t>(),
-                                    (int)b->n_items, s);
+                                    (int)b->n_items, b->bc, s);
     return launch_tb_batch<T>(A, b->lat.as<int32_t>(), b->tiles.as<int32_t>(),
-                              (int)b->n_items, steps, b->variant, s);
+                              (int)b->n_items, steps, b->variant, b->bc, s);
 }
 
 template <typename T>
@@ -878,7 +879,7 @@ hipGraphExec_t batch_graph(lbm_batch *b, int64_t launches) {
     const int H = batch_steps_per_launch(b);
     // Kernel attributes are set outside the capture (an empty launch does it).
     if (!batch_single_step(b))
-        HIP_TRY(launch_tb_batch<T>(nullptr, nullptr, nullptr, 0, H, b->variant, b->stream));
+        HIP_TRY(launch_tb_batch<T>(nullptr, nullptr, nullptr, 0, H, b->variant, b->bc, b->stream));
     HIP_TRY(hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
     for (int64_t k = 0; k < launches && err == hipSuccess; ++k)
@@ -1507,6 +1508,7 @@ int lbm_batch_create(lbm_handle *const *handles, int32_t count, void *hip_stream
     if (!b) return fail(LBM_ENOMEM, "host allocation failed");
     try {
         b->hs.assign(handles, handles + count);
+        for (int32_t i = 0; i < count; ++i) b->bc = b->bc || handles[i]->flags != 0;
         b->versions.assign((size_t)count, 0);
         b->precision = handles[0]->precision;
         b->device = dev;

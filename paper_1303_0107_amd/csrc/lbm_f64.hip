@@ -266,15 +266,16 @@ hipError_t launch_tb<double>(const SweepArgs<double> &a, const int32_t *tiles, i
 template <>
 hipError_t launch_tb_batch<double>(const SweepArgs<double> *args, const int32_t *lat,
                                    const int32_t *tiles, int n_items, int steps, int variant,
-                                   hipStream_t s) {
+                                   bool bc, hipStream_t s) {
     return sweep::launch_tb_batch_variant<f64::Cell>(args, lat, tiles, n_items, steps, variant,
-                                                     s);
+                                                     bc, s);
 }
 
 template <>
 hipError_t launch_step_batch<double>(const SweepArgs<double> *args, const int32_t *lat,
-                                     const int32_t *blocks, int n_items, hipStream_t s) {
-    return sweep::launch_step_batch<f64::Cell>(args, lat, blocks, n_items, s);
+                                     const int32_t *blocks, int n_items, bool bc,
+                                     hipStream_t s) {
+    return sweep::launch_step_batch<f64::Cell>(args, lat, blocks, n_items, bc, s);
 }
 
 template <>

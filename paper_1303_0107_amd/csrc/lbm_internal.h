@@ -176,14 +176,15 @@ hipError_t launch_tb(const SweepArgs<T> &a, const int32_t *tiles, int n_tiles, i
                      bool check, int variant, hipStream_t s);
 // The same for many lattices at once: item b is tile tiles[b] of lattice
 // lat[b] with arguments args[lat[b]] (device arrays); no residual partials.
+// bc: some member has boundary-variant flags.
 template <typename T>
 hipError_t launch_tb_batch(const SweepArgs<T> *args, const int32_t *lat, const int32_t *tiles,
-                           int n_items, int steps, int variant, hipStream_t s);
+                           int n_items, int steps, int variant, bool bc, hipStream_t s);
 // One time step of many lattices: item b is the 64 x 4 block blocks[b] of
 // lattice lat[b] with arguments args[lat[b]] (device arrays).
 template <typename T>
 hipError_t launch_step_batch(const SweepArgs<T> *args, const int32_t *lat,
-                             const int32_t *blocks, int n_items, hipStream_t s);
+                             const int32_t *blocks, int n_items, bool bc, hipStream_t s);
 int64_t sweep_blocks(int nx, int ny);
 hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
                             hipStream_t s);
@@ -243,10 +244,11 @@ hipError_t launch_tb<double>(const SweepArgs<double> &a, const int32_t *tiles, i
 template <>
 hipError_t launch_tb_batch<double>(const SweepArgs<double> *args, const int32_t *lat,
                                    const int32_t *tiles, int n_items, int steps, int variant,
-                                   hipStream_t s);
+                                   bool bc, hipStream_t s);
 template <>
 hipError_t launch_step_batch<double>(const SweepArgs<double> *args, const int32_t *lat,
-                                     const int32_t *blocks, int n_items, hipStream_t s);
+                                     const int32_t *blocks, int n_items, bool bc,
+                                     hipStream_t s);
 template <>
 hipError_t launch_macro<double>(const MacroArgs<double> &a, hipStream_t s);
 template <>
@@ -278,10 +280,11 @@ hipError_t launch_import_plane<double>(double *f, const uint16_t *cell, const do
     template <>                                                                            \
     hipError_t launch_tb_batch<T>(const SweepArgs<T> *args, const int32_t *lat,            \
                                   const int32_t *tiles, int n_items, int steps,            \
-                                  int variant, hipStream_t s);                             \
+                                  int variant, bool bc, hipStream_t s);                    \
     template <>                                                                            \
     hipError_t launch_step_batch<T>(const SweepArgs<T> *args, const int32_t *lat,          \
-                                    const int32_t *blocks, int n_items, hipStream_t s);    \
+                                    const int32_t *blocks, int n_items, bool bc,           \
+                                    hipStream_t s);                                        \
     template <>                                                                            \
     hipError_t launch_rest_cells<T>(T * f, size_t plane, const int32_t *cells, int count,  \
                                     int nx, int pitch, hipStream_t s);                     \

@@ -537,14 +537,15 @@ static inline dim3 grid_cells(int ncols, int ny) {
     template <>                                                                          \
     hipError_t launch_tb_batch<T>(const SweepArgs<T> *args, const int32_t *lat,          \
                                   const int32_t *tiles, int n_items, int steps,          \
-                                  int variant, hipStream_t s) {                          \
+                                  int variant, bool bc, hipStream_t s) {                 \
         return sweep::launch_tb_batch_variant<CELL>(args, lat, tiles, n_items, steps,    \
-                                                    variant, s);                         \
+                                                    variant, bc, s);                     \
     }                                                                                    \
     template <>                                                                          \
     hipError_t launch_step_batch<T>(const SweepArgs<T> *args, const int32_t *lat,        \
-                                    const int32_t *blocks, int n_items, hipStream_t s) { \
-        return sweep::launch_step_batch<CELL>(args, lat, blocks, n_items, s);            \
+                                    const int32_t *blocks, int n_items, bool bc,         \
+                                    hipStream_t s) {                                     \
+        return sweep::launch_step_batch<CELL>(args, lat, blocks, n_items, bc, s);        \
     }
 LBM_OFFSET_LAUNCHERS(float, F32Cell)
 LBM_OFFSET_LAUNCHERS(h16, H16Cell)

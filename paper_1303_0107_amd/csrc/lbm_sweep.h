@@ -99,8 +99,9 @@ __device__ __forceinline__ void check_terms(const SweepArgs<T> &a, size_t n,
     a.uprev[a.plane + n] = uy;
 }
 
-// One time step of the 64 x 4 cells of block (bx, by).
-template <class Cell, bool CHECK>
+// One time step of the 64 x 4 cells of block (bx, by).  BC: the lattice has
+// boundary-variant cells (flags != 0); without them those paths compile out.
+template <class Cell, bool CHECK, bool BC>
 __device__ __forceinline__ void step_body(const SweepArgs<typename Cell::T> &a, const int bx,
                                           const int by, double *part_out) {
     using CT = typename Cell::CT;
@@ -115,14 +116,14 @@ __device__ __forceinline__ void step_body(const SweepArgs<typename Cell::T> &a, 
         const size_t P = a.plane;
         // boundary velocity: the inlet profile, or a Neumann outlet's neighbour
         CT bx = type == kInlet ? (CT)a.uin[y] : CT(0), by = CT(0);
-        if (type == kOutletNeumann && (cw & kWordLeftLive)) {
+        if (BC && type == kOutletNeumann && (cw & kWordLeftLive)) {
             CT g[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) g[i] = Cell::load(a.fin[(size_t)i * P + n - 1]);
             Cell::velocity(g, bx, by);
         }
         CT f[9];
-        if (cw & kWordGeneral) {
+        if (BC && (cw & kWordGeneral)) {
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 f[i] = Cell::load(a.fin[general_src(cw, i, x, y, y, a.ny, a.flags, P, a.pitch)]);
@@ -150,9 +151,9 @@ __device__ __forceinline__ void step_body(const SweepArgs<typename Cell::T> &a, 
     }
 }
 
-template <class Cell, bool CHECK>
+template <class Cell, bool CHECK, bool BC>
 __global__ __launch_bounds__(256) void step_kernel(SweepArgs<typename Cell::T> a) {
-    step_body<Cell, CHECK>(
+    step_body<Cell, CHECK, BC>(
         a, blockIdx.x, blockIdx.y,
         CHECK ? a.partials + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 : nullptr);
 }
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(256) void step_kernel(SweepArgs<typename Cell::T> a
 // One time step of many lattices: work item b is the 64 x 4 block
 // blocks[b] (packed block row << 16 | block column) of lattice lat[b];
 // lat[b] < 0 marks a padding item.
-template <class Cell>
+template <class Cell, bool BC>
 __global__ __launch_bounds__(256) void step_batch_kernel(
     const SweepArgs<typename Cell::T> *__restrict__ args, const int32_t *__restrict__ lat,
     const int32_t *__restrict__ blocks) {
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(256) void step_batch_kernel(
     if (l < 0) return;
     const SweepArgs<typename Cell::T> a = args[l];
     const int t = blocks[blockIdx.x];
-    step_body<Cell, false>(a, t & 0xffff, t >> 16, nullptr);
+    step_body<Cell, false, BC>(a, t & 0xffff, t >> 16, nullptr);
 }
 
 // Temporal blocking.  Tile t = tiles[blockIdx.x] packs (tile row << 16 | tile
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void step_batch_kernel(
 // writes the other (one barrier per step, nothing held in registers across
 // the barrier).  Otherwise one copy updated in place: every thread keeps its
 // cells' new populations in registers until all reads of the step are done.
-template <class Cell, int RH, int H, int NT, bool PP, bool CHECK>
+template <class Cell, int RH, int H, int NT, bool PP, bool CHECK, bool BC>
 __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, const int t,
                                         const int steps, double *part_out) {
     using T = typename Cell::T;
@@ -226,14 +227,14 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
             if (v) {
                 const int gy = oy + ry;
                 CT bx = type == kInlet ? (CT)a.uin[gy] : CT(0), by = CT(0);
-                if (type == kOutletNeumann && (cw[c] & kWordLeftLive)) {
+                if (BC && type == kOutletNeumann && (cw[c] & kWordLeftLive)) {
                     CT g[9];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) g[i] = Cell::load(Ls[i * PL + ry * RW + lane - 1]);
                     Cell::velocity(g, bx, by);
                 }
                 CT f[9];
-                if (cw[c] & kWordGeneral) {
+                if (BC && (cw[c] & kWordGeneral)) {
 #pragma unroll
                     for (int i = 0; i < 9; ++i)
                         f[i] = Cell::load(Ls[general_src(cw[c], i, lane, ry, gy, a.ny, a.flags,
@@ -297,7 +298,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
 // take consecutive entries.  Within a class, entries keep row-major order.
 // Each update reads the same nine values as the dense form, so the results
 // are the same bits.  LDS: the two region copies, then PL list words.
-template <class Cell, int RH, int H, int NT, bool CHECK>
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC>
 __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T> &a, const int t,
                                                 const int steps, double *part_out) {
     using T = typename Cell::T;
@@ -399,14 +400,14 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
                 const uint32_t type = update_type(c);
                 const int gy = oy + ry;
                 CT bx = type == kInlet ? (CT)a.uin[gy] : CT(0), by = CT(0);
-                if (type == kOutletNeumann && (c & kWordLeftLive)) {
+                if (BC && type == kOutletNeumann && (c & kWordLeftLive)) {
                     CT g[9];
 #pragma unroll
                     for (int i = 0; i < 9; ++i) g[i] = Cell::load(Ls[i * PL + pos - 1]);
                     Cell::velocity(g, bx, by);
                 }
                 CT f[9];
-                if (c & kWordGeneral) {
+                if (BC && (c & kWordGeneral)) {
 #pragma unroll
                     for (int i = 0; i < 9; ++i)
                         f[i] = Cell::load(Ls[general_src(c, i, lx, ry, gy, a.ny, a.flags, PL, RW)]);
@@ -445,34 +446,34 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
 }
 
 // One region shape: rows x 64 cells, halo H, dense or compacted.
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK>
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK, bool BC>
 __device__ __forceinline__ void tb_dispatch(const SweepArgs<typename Cell::T> &a, const int t,
                                             const int steps, double *part_out) {
     if constexpr (COMPACT)
-        tb_body_compact<Cell, RH, H, NT, CHECK>(a, t, steps, part_out);
+        tb_body_compact<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
     else
-        tb_body<Cell, RH, H, NT, PP, CHECK>(a, t, steps, part_out);
+        tb_body<Cell, RH, H, NT, PP, CHECK, BC>(a, t, steps, part_out);
 }
 
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK>
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK, bool BC>
 __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
                                                 const int32_t *__restrict__ tiles,
                                                 int steps) {
-    tb_dispatch<Cell, RH, H, NT, PP, COMPACT, CHECK>(
+    tb_dispatch<Cell, RH, H, NT, PP, COMPACT, CHECK, BC>(
         a, tiles[blockIdx.x], steps, CHECK ? a.partials + (size_t)blockIdx.x * 4 : nullptr);
 }
 
 // Many lattices in one launch: work item b is tile tiles[b] of lattice
 // lat[b], whose arguments are args[lat[b]]; lat[b] < 0 marks a padding item
 // (the whole workgroup leaves at once, before any barrier).
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT>
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool BC>
 __global__ __launch_bounds__(NT) void tb_batch_kernel(
     const SweepArgs<typename Cell::T> *__restrict__ args, const int32_t *__restrict__ lat,
     const int32_t *__restrict__ tiles, int steps) {
     const int l = lat[blockIdx.x];
     if (l < 0) return;
     const SweepArgs<typename Cell::T> a = args[l];
-    tb_dispatch<Cell, RH, H, NT, PP, COMPACT, false>(a, tiles[blockIdx.x], steps, nullptr);
+    tb_dispatch<Cell, RH, H, NT, PP, COMPACT, false, BC>(a, tiles[blockIdx.x], steps, nullptr);
 }
 
 // Dynamic LDS of one region shape.
@@ -486,10 +487,35 @@ constexpr size_t tb_lds_bytes() {
 template <class Cell>
 hipError_t launch_step(const SweepArgs<typename Cell::T> &a, bool check, hipStream_t s) {
     const dim3 g((unsigned)((a.nx + 63) / 64), (unsigned)((a.ny + 3) / 4)), b(64, 4);
-    if (check)
-        hipLaunchKernelGGL((step_kernel<Cell, true>), g, b, 0, s, a);
+    const bool bc = a.flags != 0;
+    if (check && bc)
+        hipLaunchKernelGGL((step_kernel<Cell, true, true>), g, b, 0, s, a);
+    else if (check)
+        hipLaunchKernelGGL((step_kernel<Cell, true, false>), g, b, 0, s, a);
+    else if (bc)
+        hipLaunchKernelGGL((step_kernel<Cell, false, true>), g, b, 0, s, a);
     else
-        hipLaunchKernelGGL((step_kernel<Cell, false>), g, b, 0, s, a);
+        hipLaunchKernelGGL((step_kernel<Cell, false, false>), g, b, 0, s, a);
+    return hipGetLastError();
+}
+
+// Raise a kernel's dynamic LDS limit; `done` is the caller's per-kernel flag.
+inline hipError_t set_lds(const void *k, size_t lds, bool &done) {
+    if (done) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK, bool BC>
+hipError_t launch_tb_one(const SweepArgs<typename Cell::T> &a, const int32_t *tiles, int n_tiles,
+                         int steps, hipStream_t s) {
+    const size_t lds = tb_lds_bytes<typename Cell::T, RH, PP, COMPACT>();
+    auto k = tb_kernel<Cell, RH, H, NT, PP, COMPACT, CHECK, BC>;
+    static bool configured = false;  // one flag per kernel instantiation
+    const hipError_t e = set_lds((const void *)k, lds, configured);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)n_tiles), dim3(NT), lds, s, a, tiles, steps);
     return hipGetLastError();
 }
 
@@ -498,50 +524,51 @@ hipError_t launch_tb(const SweepArgs<typename Cell::T> &a, const int32_t *tiles,
                      int steps, bool check, hipStream_t s) {
     if (n_tiles <= 0 || steps <= 0) return hipSuccess;
     if (steps > H) return hipErrorInvalidValue;
-    const size_t lds = tb_lds_bytes<typename Cell::T, RH, PP, COMPACT>();
-    auto k_plain = tb_kernel<Cell, RH, H, NT, PP, COMPACT, false>;
-    auto k_check = tb_kernel<Cell, RH, H, NT, PP, COMPACT, true>;
-    static bool configured = false;
-    if (!configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_plain,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)k_check,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        configured = true;
-    }
+    const bool bc = a.flags != 0;
+    if (check && bc)
+        return launch_tb_one<Cell, RH, H, NT, PP, COMPACT, true, true>(a, tiles, n_tiles, steps, s);
     if (check)
-        hipLaunchKernelGGL(k_check, dim3((unsigned)n_tiles), dim3(NT), lds, s, a, tiles, steps);
-    else
-        hipLaunchKernelGGL(k_plain, dim3((unsigned)n_tiles), dim3(NT), lds, s, a, tiles, steps);
-    return hipGetLastError();
+        return launch_tb_one<Cell, RH, H, NT, PP, COMPACT, true, false>(a, tiles, n_tiles, steps, s);
+    if (bc)
+        return launch_tb_one<Cell, RH, H, NT, PP, COMPACT, false, true>(a, tiles, n_tiles, steps, s);
+    return launch_tb_one<Cell, RH, H, NT, PP, COMPACT, false, false>(a, tiles, n_tiles, steps, s);
 }
 
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT>
-hipError_t launch_tb_batch(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
-                           const int32_t *tiles, int n_items, int steps, hipStream_t s) {
-    if (steps > H) return hipErrorInvalidValue;
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool BC>
+hipError_t launch_tb_batch_one(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
+                               const int32_t *tiles, int n_items, int steps, hipStream_t s) {
     const size_t lds = tb_lds_bytes<typename Cell::T, RH, PP, COMPACT>();
-    auto k = tb_batch_kernel<Cell, RH, H, NT, PP, COMPACT>;
-    static bool configured = false;
-    if (!configured) {  // also on an empty call, so that it can precede a graph capture
-        const hipError_t e = hipFuncSetAttribute(
-            (const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        configured = true;
-    }
+    auto k = tb_batch_kernel<Cell, RH, H, NT, PP, COMPACT, BC>;
+    static bool configured = false;  // one flag per kernel instantiation; set also on an
+                                     // empty call, so that it can precede a graph capture
+    const hipError_t e = set_lds((const void *)k, lds, configured);
+    if (e != hipSuccess) return e;
     if (n_items <= 0 || steps <= 0) return hipSuccess;
     hipLaunchKernelGGL(k, dim3((unsigned)n_items), dim3(NT), lds, s, args, lat, tiles, steps);
     return hipGetLastError();
 }
 
+template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT>
+hipError_t launch_tb_batch(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
+                           const int32_t *tiles, int n_items, int steps, bool bc, hipStream_t s) {
+    if (steps > H) return hipErrorInvalidValue;
+    if (bc)
+        return launch_tb_batch_one<Cell, RH, H, NT, PP, COMPACT, true>(args, lat, tiles, n_items,
+                                                                       steps, s);
+    return launch_tb_batch_one<Cell, RH, H, NT, PP, COMPACT, false>(args, lat, tiles, n_items,
+                                                                    steps, s);
+}
+
 template <class Cell>
 hipError_t launch_step_batch(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
-                             const int32_t *blocks, int n_items, hipStream_t s) {
+                             const int32_t *blocks, int n_items, bool bc, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL((step_batch_kernel<Cell>), dim3((unsigned)n_items), dim3(64, 4), 0, s,
-                       args, lat, blocks);
+    if (bc)
+        hipLaunchKernelGGL((step_batch_kernel<Cell, true>), dim3((unsigned)n_items), dim3(64, 4),
+                           0, s, args, lat, blocks);
+    else
+        hipLaunchKernelGGL((step_batch_kernel<Cell, false>), dim3((unsigned)n_items), dim3(64, 4),
+                           0, s, args, lat, blocks);
     return hipGetLastError();
 }
 
@@ -564,15 +591,15 @@ hipError_t launch_tb_variant(const SweepArgs<typename Cell::T> &a, const int32_t
 template <class Cell, int V = 0>
 hipError_t launch_tb_batch_variant(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
                                    const int32_t *tiles, int n_items, int steps, int variant,
-                                   hipStream_t s) {
+                                   bool bc, hipStream_t s) {
     using T = typename Cell::T;
     if constexpr (V < TbVariants<T>::count) {
         if (variant == V)
             return launch_tb_batch<Cell, TbVariants<T>::v[V].rows, TbVariants<T>::v[V].halo,
                                    kTbThreads, true, TbVariants<T>::v[V].compact>(
-                args, lat, tiles, n_items, steps, s);
+                args, lat, tiles, n_items, steps, bc, s);
         return launch_tb_batch_variant<Cell, V + 1>(args, lat, tiles, n_items, steps, variant,
-                                                    s);
+                                                    bc, s);
     } else {
         return hipErrorInvalidValue;
     }
