@@ -116,7 +116,7 @@ def bench_batch(args) -> int:
     prec = {"f64": lbm.LBM_F64, "f32": lbm.LBM_F32, "f16": lbm.LBM_F32_S_F16,
             "bf16": lbm.LBM_F32_S_BF16}[args.precision]
     s_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[args.precision]
-    arith = "f64" if args.precision in ("f64", "f32") else "f32"
+    arith = "f64" if args.precision == "f64" else "f32"
     cands = I.batch_candidates(count=args.batch_count, seed=4)
     types = [c.types() for c in cands]
     N = sum(t.size for t in types)
@@ -292,14 +292,14 @@ def bench_serve(args) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64/f32",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
             "workload": SERVE_WORKLOAD, "requests": len(reqs),
             "arrivals": f"Poisson {args.serve_rate}/s for {args.serve_seconds} s, seed 5",
             "lattices": "nx = 64 round(256 2^U(0,4) / 64), ny = nx/2; generator as the "
                         "batched candidates",
-            "mix": "FP32 / FP16 offset storage 50/50 (arithmetic f64 / f32); solve 500 steps / "
+            "mix": "FP32 / FP16 offset storage 50/50 (float arithmetic); solve 500 steps / "
                    "optimise 100 steps + 20 x (exchange step + 40 steps), 50/50",
             "hbm_budget_gb": args.hbm_budget_gb, "max_sessions": args.max_sessions,
             "quantum": args.quantum,
@@ -336,7 +336,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["f32", "f64", "f16", "bf16"], default="f32",
                     help="population storage (f64: double storage and arithmetic; f32: float "
-                         "storage, double arithmetic; f16/bf16: 16-bit storage, float arithmetic)")
+                         "storage, float arithmetic; f16/bf16: 16-bit storage, float arithmetic)")
     ap.add_argument("--workload", default="distributor-1024x512-L3")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--cap", type=int, default=200000, help="step cap per solve")
@@ -381,7 +381,7 @@ def main() -> int:
     prec = {"f64": lbm.LBM_F64, "f32": lbm.LBM_F32, "f16": lbm.LBM_F32_S_F16,
             "bf16": lbm.LBM_F32_S_BF16}[args.precision]
     s_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[args.precision]
-    arith = "f64" if args.precision in ("f64", "f32") else "f32"
+    arith = "f64" if args.precision == "f64" else "f32"
     frac = w.extra.get("frac", 0.01)
     k = 100
 

@@ -78,19 +78,12 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid,
 }
 
 // ---------------------------------------------------------------------------
-#ifndef LBM_F32_COMPUTE
-#define LBM_F32_COMPUTE double
-#endif
-#ifndef LBM_F32_POLY
-#define LBM_F32_POLY LBM_F32_COMPUTE
-#endif
-
 // One cell of one time step on offsets d_i = f_i - w_i stored as T (float,
 // or 16-bit for the reduced-storage forms), arithmetic in CT, velocity
-// polynomials in PT.  With float storage CT = PT = double: the rounding of
-// float arithmetic, not that of the stored offsets, would dominate the error
-// of steady fields.  The 16-bit forms relax in float, their storage rounding
-// being far larger than float arithmetic's.  Zou-He closure on inlet
+// polynomials in PT (all forms: float).  The relaxation restores exact mass
+// and momentum conservation after rounding (see update); without that, the
+// rounded weights bias every step the same way and float arithmetic, not
+// the storage, dominated the error of steady fields.  Zou-He closure on inlet
 // (velocity u_in, unknowns 1, 5, 8) and outlet cells (density rho_out, zero
 // transverse velocity, unknowns 3, 6, 7), moments (Eq. 2), BGK relaxation
 // (Eq. 1) to the equilibrium of Sec. 2.1 written for offsets:
@@ -166,27 +159,42 @@ struct OffsetCell {
         // sign of the odd part B = 3 cu.
         const PT pux = (PT)ux, puy = (PT)uy;
         const PT puu15 = PT(1.5) * (pux * pux + puy * puy);
-        auto relax_pair = [&](int i, int j, PT cu, CT w) {
+        // With the weights rounded (to float), the equilibrium's mass and
+        // momentum differ from dr and (jx, jy) by ~1e-8 relative, every step,
+        // with a fixed sign: a bias that the flow's slowest mode accumulates
+        // over thousands of steps (a steady-state error ~1e-4).  So relax by
+        // increments D_i = om (e_i - d_i) and restore exact conservation: the
+        // (1,3) and (2,4) pairs take the momentum defects, D_0 the mass
+        // defect.  Every sum is in mirror-symmetric order, so a y-reflection
+        // maps each increment onto its mirror image bit for bit.
+        CT D[9];
+        auto incr_pair = [&](int i, int j, PT cu, CT w) {
             const PT A = PT(4.5) * cu * cu - puu15;
             const PT B = PT(3) * cu;
-            const CT ei = w * (dr + rho * (CT)(A + B));
-            const CT ej = w * (dr + rho * (CT)(A - B));
-            d[i] = d[i] + om * (ei - d[i]);
-            d[j] = d[j] + om * (ej - d[j]);
+            D[i] = om * (w * (dr + rho * (CT)(A + B)) - d[i]);
+            D[j] = om * (w * (dr + rho * (CT)(A - B)) - d[j]);
         };
-        const CT w0 = CT(4) / CT(9), w1 = CT(1) / CT(9), w5 = CT(1) / CT(36);
-        d[0] = d[0] + om * (w0 * (dr - rho * (CT)puu15) - d[0]);
-        relax_pair(1, 3, pux, w1);
-        relax_pair(2, 4, puy, w1);
-        relax_pair(5, 7, pux + puy, w5);
-        relax_pair(6, 8, puy - pux, w5);
+        const CT w1 = CT(1) / CT(9), w5 = CT(1) / CT(36);
+        incr_pair(1, 3, pux, w1);
+        incr_pair(2, 4, puy, w1);
+        incr_pair(5, 7, pux + puy, w5);
+        incr_pair(6, 8, puy - pux, w5);
+        const CT mx = (D[1] - D[3]) + ((D[5] - D[7]) + (D[8] - D[6]));
+        const CT my = (D[2] - D[4]) + ((D[5] - D[8]) + (D[6] - D[7]));
+        D[1] = D[1] - CT(0.5) * mx;
+        D[3] = D[3] + CT(0.5) * mx;
+        D[2] = D[2] - CT(0.5) * my;
+        D[4] = D[4] + CT(0.5) * my;
+        D[0] = -(((D[1] + D[3]) + (D[2] + D[4])) + ((D[5] + D[8]) + (D[6] + D[7])));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = d[i] + D[i];
         mass = 1.0 + (double)dr;
         ux_out = (double)ux;
         uy_out = (double)uy;
     }
 };
 
-using F32Cell = OffsetCell<float, LBM_F32_COMPUTE, LBM_F32_POLY>;
+using F32Cell = OffsetCell<float, float, float>;
 using H16Cell = OffsetCell<h16, float, float>;
 using BF16Cell = OffsetCell<bf16, float, float>;
 

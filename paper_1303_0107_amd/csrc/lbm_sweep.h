@@ -196,6 +196,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
     const bool col_in = gx >= 0 && gx < a.nx;
 
     uint32_t cw[CPT];
+    UinT<T> uin[CPT];  // inlet velocity of the thread's cells, read once per launch
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int ry = wave + c * NW, gy = oy + ry;
@@ -203,6 +204,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
         const size_t n = in ? (size_t)gy * a.pitch + gx : 0;
         cw[c] = in ? a.cell[n] : 0u;
         const bool live = in && cell_type(cw[c]) != kSolid;
+        uin[c] = (in && cell_type(cw[c]) == kInlet) ? a.uin[gy] : UinT<T>(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             L[i * PL + ry * RW + lane] = live ? a.fin[(size_t)i * a.plane + n] : Cell::store(CT(0));
@@ -226,7 +228,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
             upd[c] = v;
             if (v) {
                 const int gy = oy + ry;
-                CT bx = type == kInlet ? (CT)a.uin[gy] : CT(0), by = CT(0);
+                CT bx = type == kInlet ? (CT)uin[c] : CT(0), by = CT(0);
                 if (BC && type == kOutletNeumann && (cw[c] & kWordLeftLive)) {
                     CT g[9];
 #pragma unroll
@@ -376,10 +378,13 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
     __syncthreads();
     const int n_all = cls_base[0];
     uint32_t ent[CPT];
+    UinT<T> uin[CPT];  // inlet velocity of the thread's entries, read once per launch
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int j = threadIdx.x + m * NT;
         ent[m] = j < n_all ? list[j] : 0u;
+        const bool inlet = j < n_all && cell_type(ent[m] >> 16) == kInlet;
+        uin[m] = inlet ? a.uin[oy + (int)(ent[m] & 0xffffu) / RW] : UinT<T>(0);
     }
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
@@ -399,7 +404,7 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
                 const int ry = pos / RW, lx = pos % RW;
                 const uint32_t type = update_type(c);
                 const int gy = oy + ry;
-                CT bx = type == kInlet ? (CT)a.uin[gy] : CT(0), by = CT(0);
+                CT bx = type == kInlet ? (CT)uin[m] : CT(0), by = CT(0);
                 if (BC && type == kOutletNeumann && (c & kWordLeftLive)) {
                     CT g[9];
 #pragma unroll
