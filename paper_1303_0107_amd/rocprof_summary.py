@@ -13,7 +13,8 @@ import collections
 import csv
 
 
-SHORT = [("lbm::OffsetCell<float, double, double>", "F32Cell"),
+SHORT = [("lbm::OffsetCell<float, float, float>", "F32Cell"),
+         ("lbm::OffsetCell<float, double, double>", "F32Cell(double arithmetic)"),
          ("lbm::OffsetCell<_Float16, float, float>", "H16Cell"),
          ("lbm::OffsetCell<__hip_bfloat16, float, float>", "BF16Cell"),
          ("lbm::f64::Cell", "F64Cell"), ("void ", ""), ("lbm::sweep::", ""), ("lbm::", "")]
