@@ -398,8 +398,10 @@ typedef struct {
     size_t hbm_budget;      /* bytes of lbm_footprint_bytes admitted at once   */
     int32_t max_sessions;   /* active sessions at once (>= 1)                  */
     int32_t quantum;        /* time steps per round at most (>= 1)             */
-    int32_t variant;        /* batch variant (lbm_batch_configure), -1: default */
-    int32_t order;          /* batch work-list order (0 or 1)                  */
+    int32_t variant;        /* batch variant (lbm_batch_configure); -1: chosen
+                               by lbm_batch_tune once per precision, on the
+                               first batch of >= 8 sessions                   */
+    int32_t order;          /* batch work-list order (0 or 1) with variant >= 0 */
 } lbm_server_config;
 
 typedef struct {

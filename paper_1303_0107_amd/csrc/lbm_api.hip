@@ -255,6 +255,9 @@ struct lbm_handle {
     bool use_tb = true;
     DeviceBuffer tiles;
     std::vector<int32_t> tile_host;
+    int32_t *tile_pinned = nullptr;    // staging of the tile-list upload
+    size_t tile_pinned_count = 0;
+    hipEvent_t tile_copied = nullptr;  // recorded after the last upload
     int n_tiles = 0;
     int tb_variant = 0;         // region shape (index into the compiled shapes)
     uint64_t mask_version = 0;  // bumped whenever the mask changes
@@ -279,6 +282,11 @@ struct lbm_handle {
         drop_graphs();
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
         if (pinned) (void)hipHostFree(pinned);
+        if (tile_copied) {
+            (void)hipEventSynchronize(tile_copied);
+            (void)hipEventDestroy(tile_copied);
+        }
+        if (tile_pinned) (void)hipHostFree(tile_pinned);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
     }
@@ -397,11 +405,26 @@ void rebuild_tiles(lbm_handle *h) {
     h->tile_host = tile_list(h, tile_width(h->precision, h->tb_variant),
                              tile_height(h->precision, h->tb_variant));
     h->n_tiles = (int)h->tile_host.size();
-    h->tiles.ensure(max_tile_count(h->nx, h->ny, h->precision) * sizeof(int32_t));
-    if (h->n_tiles > 0)
-        HIP_TRY(hipMemcpyAsync(h->tiles.p, h->tile_host.data(), h->n_tiles * sizeof(int32_t),
+    const size_t cap = max_tile_count(h->nx, h->ny, h->precision);
+    h->tiles.ensure(cap * sizeof(int32_t));
+    if (!h->tile_copied) HIP_TRY(hipEventCreateWithFlags(&h->tile_copied, hipEventDisableTiming));
+    // The staging buffer may still feed the previous upload: wait for it.
+    HIP_TRY(hipEventSynchronize(h->tile_copied));
+    if (h->tile_pinned_count < cap) {
+        if (h->tile_pinned) (void)hipHostFree(h->tile_pinned);
+        h->tile_pinned = nullptr;
+        h->tile_pinned_count = 0;
+        void *p = nullptr;
+        HIP_TRY(hipHostMalloc(&p, cap * sizeof(int32_t), hipHostMallocDefault));
+        h->tile_pinned = static_cast<int32_t *>(p);
+        h->tile_pinned_count = cap;
+    }
+    if (h->n_tiles > 0) {
+        std::memcpy(h->tile_pinned, h->tile_host.data(), h->n_tiles * sizeof(int32_t));
+        HIP_TRY(hipMemcpyAsync(h->tiles.p, h->tile_pinned, h->n_tiles * sizeof(int32_t),
                                hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    HIP_TRY(hipEventRecord(h->tile_copied, h->stream));
 }
 
 // Parabolic inlet profile (Sec. 3.3) on each maximal run of inlet rows,
@@ -1302,19 +1325,23 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
         }
         HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
                                    h->ny, h->pitch, h->flags, h->stream));
-        unsigned long long *fc = h->red.as<unsigned long long>() + 48;
-        HIP_TRY(hipMemsetAsync(fc, 0, sizeof(unsigned long long), h->stream));
-        HIP_TRY(launch_count_type(h->types.as<uint8_t>(), N, (uint8_t)LBM_FLUID, fc,
-                                  h->stream));
-        HIP_TRY(hipMemcpyAsync(h->pinned, fc, sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
-        const int64_t nf_after =
-            (int64_t) * reinterpret_cast<unsigned long long *>(h->pinned);
+        // Constant volume by construction (k_eff fluid cells out, k_eff
+        // solid cells in); checked on the host mirror as the flips apply:
+        // every removed cell must have been fluid and every added one solid,
+        // each listed once.
+        int64_t nf_after = nf;
         for (int64_t k = 0; k < keff; ++k) {
-            h->host_types[rem[k]] = LBM_SOLID;
-            h->host_types[add[k]] = LBM_FLUID;
+            uint8_t &tr = h->host_types[rem[k]];
+            nf_after -= tr == LBM_FLUID ? 1 : 0;
+            tr = tr == LBM_FLUID ? (uint8_t)LBM_SOLID : (uint8_t)0xff;
         }
+        for (int64_t k = 0; k < keff; ++k) {
+            uint8_t &ta = h->host_types[add[k]];
+            nf_after += ta == LBM_SOLID ? 1 : 0;
+            ta = ta == LBM_SOLID ? (uint8_t)LBM_FLUID : (uint8_t)0xff;
+        }
+        for (int64_t k = 0; k < keff; ++k)
+            if (h->host_types[rem[k]] == 0xff || h->host_types[add[k]] == 0xff) nf_after = -1;
         h->last_removed.assign(rem.begin(), rem.end());
         h->last_added.assign(add.begin(), add.end());
         if (keff > 0) {

@@ -165,10 +165,13 @@ __global__ __launch_bounds__(256) void mass_kernel(MacroArgs<double> a,
 // outlet k; thread n_out sums x momentum and density over the inlet cells
 // and density over all outlet cells (one running sum each).  out layout:
 // [flow_0..flow_{n-1}, unused n, flow_in, rho_in, count_in, count_out, rho_out]
-__global__ void boundary_kernel(MacroArgs<double> a, const int32_t *out_y0,
-                                const int32_t *out_y1, int n_out, double *out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > n_out) return;
+__global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<double> a,
+                                                      const int32_t *out_y0,
+                                                      const int32_t *out_y1, int n_out,
+                                                      double *out) {
+    // One wave per task; lanes load 64 rows at once, the sums take them in
+    // increasing y one at a time (the oracle's sequential order).
+    const int k = blockIdx.x, lane = threadIdx.x;
     auto at = [&](size_t n, double &r, double &mx) {
         double f[9], my;
 #pragma unroll
@@ -176,36 +179,55 @@ __global__ void boundary_kernel(MacroArgs<double> a, const int32_t *out_y0,
         moments(f, r, mx, my);
     };
     if (k < n_out) {
+        const int y0 = out_y0[k], y1 = out_y1[k];
         double fl = 0.0;
-        for (int y = out_y0[k]; y <= out_y1[k]; ++y) {
-            double r, mx;
-            at((size_t)y * a.pitch + (a.nx - 1), r, mx);
-            fl += mx;
+        for (int c = y0; c <= y1; c += 64) {
+            double r = 0.0, mx = 0.0;
+            if (c + lane <= y1) at((size_t)(c + lane) * a.pitch + (a.nx - 1), r, mx);
+            const int m = min(64, y1 - c + 1);
+            for (int t = 0; t < m; ++t) fl += __shfl(mx, t, 64);
         }
-        out[k] = fl;
-        out[n_out + k] = 0.0;
+        if (lane == 0) {
+            out[k] = fl;
+            out[n_out + k] = 0.0;
+        }
     } else {
         double fl = 0.0, rin = 0.0, rout = 0.0, cin = 0.0, cout = 0.0;
-        for (int y = 0; y < a.ny; ++y) {
-            const size_t n0 = (size_t)y * a.pitch;
-            double r, mx;
-            if (cell_type(a.cell[n0 + a.nx - 1]) == kOutlet) {
-                at(n0 + a.nx - 1, r, mx);
-                rout += r;
-                cout += 1.0;
+        for (int c = 0; c < a.ny; c += 64) {
+            const int y = c + lane;
+            double ro = 0.0, ri = 0.0, mi = 0.0, mo;
+            int is_out = 0, is_in = 0;
+            if (y < a.ny) {
+                const size_t n0 = (size_t)y * a.pitch;
+                if (cell_type(a.cell[n0 + a.nx - 1]) == kOutlet) {
+                    at(n0 + a.nx - 1, ro, mo);
+                    is_out = 1;
+                }
+                if (cell_type(a.cell[n0]) == kInlet) {
+                    at(n0, ri, mi);
+                    is_in = 1;
+                }
             }
-            if (cell_type(a.cell[n0]) == kInlet) {
-                at(n0, r, mx);
-                fl += mx;
-                rin += r;
-                cin += 1.0;
+            const int m = min(64, a.ny - c);
+            for (int t = 0; t < m; ++t) {
+                if (__shfl(is_out, t, 64)) {
+                    rout += __shfl(ro, t, 64);
+                    cout += 1.0;
+                }
+                if (__shfl(is_in, t, 64)) {
+                    fl += __shfl(mi, t, 64);
+                    rin += __shfl(ri, t, 64);
+                    cin += 1.0;
+                }
             }
         }
-        out[2 * n_out + 0] = fl;
-        out[2 * n_out + 1] = rin;
-        out[2 * n_out + 2] = cin;
-        out[2 * n_out + 3] = cout;
-        out[2 * n_out + 4] = rout;
+        if (lane == 0) {
+            out[2 * n_out + 0] = fl;
+            out[2 * n_out + 1] = rin;
+            out[2 * n_out + 2] = cin;
+            out[2 * n_out + 3] = cout;
+            out[2 * n_out + 4] = rout;
+        }
     }
 }
 
@@ -296,9 +318,8 @@ template <>
 hipError_t launch_boundary<double>(const MacroArgs<double> &a, const int32_t *y0,
                                    const int32_t *y1, int n_out, double *out,
                                    hipStream_t s) {
-    const int threads = n_out + 1;
-    hipLaunchKernelGGL(f64::boundary_kernel, dim3((threads + 63) / 64), dim3(64), 0, s, a,
-                       y0, y1, n_out, out);
+    hipLaunchKernelGGL(f64::boundary_kernel, dim3((unsigned)(n_out + 1)), dim3(64), 0, s, a, y0,
+                       y1, n_out, out);
     return hipGetLastError();
 }
 

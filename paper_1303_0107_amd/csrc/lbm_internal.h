@@ -232,8 +232,6 @@ hipError_t launch_select(const uint64_t *key, const uint64_t *hash, const int32_
 hipError_t launch_flip(uint8_t *types, const int32_t *removed,
                        const int32_t *added, int k_eff, double *removed_rho,
                        const double *rho, hipStream_t s);
-hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
-                             unsigned long long *out, hipStream_t s);
 
 // Double-precision specialisations, defined in lbm_f64.hip.
 template <>

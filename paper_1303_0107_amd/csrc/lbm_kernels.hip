@@ -18,6 +18,8 @@
 //                bits 8..9 the cell type.
 //   two population buffers, read one / write the other each step.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include <cstring>
@@ -278,11 +280,13 @@ __global__ __launch_bounds__(256) void mass_kernel(MacroArgs<T> a,
 // [flow_0..flow_{n-1}, rho_0..rho_{n-1}, flow_in, rho_in, count_in,
 //  count_out, rho_out]
 template <typename T>
-__global__ void boundary_kernel(MacroArgs<T> a, const int32_t *out_y0,
-                                const int32_t *out_y1, int n_out,
-                                double *out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > n_out) return;
+__global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<T> a, const int32_t *out_y0,
+                                                      const int32_t *out_y1, int n_out,
+                                                      double *out) {
+    // One wave per task (outlet k, or k = n_out: inlet and all outlet cells).
+    // Lanes load 64 rows at once; the sums then take them in increasing y,
+    // one row at a time, so every sum has the order of a sequential loop.
+    const int k = blockIdx.x, lane = threadIdx.x;
     auto moments = [&](size_t n, double &rho, double &jx) {
         double d[9];
 #pragma unroll
@@ -292,37 +296,58 @@ __global__ void boundary_kernel(MacroArgs<T> a, const int32_t *out_y0,
         rho = 1.0 + dr;
     };
     if (k < n_out) {
+        const int y0 = out_y0[k], y1 = out_y1[k];
         double fl = 0.0, rs = 0.0;
-        for (int y = out_y0[k]; y <= out_y1[k]; ++y) {
-            double r, j;
-            moments((size_t)y * a.pitch + (a.nx - 1), r, j);
-            fl += j;
-            rs += r;
+        for (int c = y0; c <= y1; c += 64) {
+            double r = 0.0, j = 0.0;
+            if (c + lane <= y1) moments((size_t)(c + lane) * a.pitch + (a.nx - 1), r, j);
+            const int m = min(64, y1 - c + 1);
+            for (int t = 0; t < m; ++t) {
+                fl += __shfl(j, t, 64);
+                rs += __shfl(r, t, 64);
+            }
         }
-        out[k] = fl;
-        out[n_out + k] = rs;
+        if (lane == 0) {
+            out[k] = fl;
+            out[n_out + k] = rs;
+        }
     } else {
         double fl = 0.0, rs = 0.0, cnt = 0.0, cnt_out = 0.0, rout = 0.0;
-        for (int y = 0; y < a.ny; ++y) {
-            const size_t n = (size_t)y * a.pitch;
-            double r, j;
-            if (cell_type(a.cell[n + a.nx - 1]) == kOutlet) {
-                moments(n + a.nx - 1, r, j);
-                rout += r;
-                cnt_out += 1.0;
+        for (int c = 0; c < a.ny; c += 64) {
+            const int y = c + lane;
+            double ro = 0.0, ri = 0.0, ji = 0.0, jo;
+            int is_out = 0, is_in = 0;
+            if (y < a.ny) {
+                const size_t n = (size_t)y * a.pitch;
+                if (cell_type(a.cell[n + a.nx - 1]) == kOutlet) {
+                    moments(n + a.nx - 1, ro, jo);
+                    is_out = 1;
+                }
+                if (cell_type(a.cell[n]) == kInlet) {
+                    moments(n, ri, ji);
+                    is_in = 1;
+                }
             }
-            if (cell_type(a.cell[n]) == kInlet) {
-                moments(n, r, j);
-                fl += j;
-                rs += r;
-                cnt += 1.0;
+            const int m = min(64, a.ny - c);
+            for (int t = 0; t < m; ++t) {  // the same order as a loop over y
+                if (__shfl(is_out, t, 64)) {
+                    rout += __shfl(ro, t, 64);
+                    cnt_out += 1.0;
+                }
+                if (__shfl(is_in, t, 64)) {
+                    fl += __shfl(ji, t, 64);
+                    rs += __shfl(ri, t, 64);
+                    cnt += 1.0;
+                }
             }
         }
-        out[2 * n_out + 0] = fl;
-        out[2 * n_out + 1] = rs;
-        out[2 * n_out + 2] = cnt;
-        out[2 * n_out + 3] = cnt_out;
-        out[2 * n_out + 4] = rout;
+        if (lane == 0) {
+            out[2 * n_out + 0] = fl;
+            out[2 * n_out + 1] = rs;
+            out[2 * n_out + 2] = cnt;
+            out[2 * n_out + 3] = cnt_out;
+            out[2 * n_out + 4] = rout;
+        }
     }
 }
 
@@ -513,18 +538,6 @@ __global__ void removed_rho_kernel(const double *rho, const int32_t *removed, in
     if (k < k_eff) out[k] = rho[removed[k]];
 }
 
-__global__ __launch_bounds__(256) void count_type_kernel(const uint8_t *types,
-                                                         size_t count,
-                                                         uint8_t which,
-                                                         unsigned long long *out) {
-    unsigned long long c = 0;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count;
-         i += (size_t)gridDim.x * 256)
-        c += types[i] == which;
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
-}
-
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 static inline dim3 grid_cells(int ncols, int ny) {
@@ -596,9 +609,8 @@ template <typename T>
 hipError_t launch_boundary(const MacroArgs<T> &a, const int32_t *y0,
                            const int32_t *y1, int n_out, double *out,
                            hipStream_t s) {
-    const int threads = n_out + 1;
-    hipLaunchKernelGGL(boundary_kernel<T>, dim3((threads + 63) / 64), dim3(64),
-                       0, s, a, y0, y1, n_out, out);
+    hipLaunchKernelGGL(boundary_kernel<T>, dim3((unsigned)(n_out + 1)), dim3(64), 0, s, a, y0,
+                       y1, n_out, out);
     return hipGetLastError();
 }
 
@@ -678,16 +690,6 @@ hipError_t launch_flip(uint8_t *types, const int32_t *removed,
     return hipGetLastError();
 }
 
-hipError_t launch_count_type(const uint8_t *types, size_t count, uint8_t which,
-                             unsigned long long *out, hipStream_t s) {
-    size_t blocks = (count + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(count_type_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                       s, types, count, which, out);
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // State digest: sum mod 2^64 over cells of SplitMix64 of each stored
 // population's bits mixed with its logical position, plus each cell's type.
@@ -703,14 +705,15 @@ __global__ __launch_bounds__(256) void digest_kernel(const T *f, const uint16_t 
                                                      const uint8_t *types, int nx, int ny,
                                                      int pitch, size_t plane,
                                                      unsigned long long *out) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
+    // Grid-stride over logical cells; one atomic per workgroup.
+    __shared__ uint64_t part[4];
+    const uint64_t N = (uint64_t)nx * (uint64_t)ny;
     uint64_t acc = 0;
-    if (x < nx && y < ny) {
+    for (uint64_t l = (uint64_t)blockIdx.x * 256 + threadIdx.x; l < N;
+         l += (uint64_t)gridDim.x * 256) {
+        const int y = (int)(l / (uint64_t)nx), x = (int)(l % (uint64_t)nx);
         const size_t n = (size_t)y * pitch + x;
-        const uint64_t l = (uint64_t)y * (uint64_t)nx + (uint64_t)x;
-        const uint8_t t = types[l];
-        acc += splitmix64((uint64_t)t ^ (l << 8) ^ 0xd1b54a32d192ed03ull);
+        acc += splitmix64((uint64_t)types[l] ^ (l << 8) ^ 0xd1b54a32d192ed03ull);
         if (cell_type(cell[n]) != kSolid) {
 #pragma unroll
             for (int i = 0; i < 9; ++i)
@@ -720,15 +723,22 @@ __global__ __launch_bounds__(256) void digest_kernel(const T *f, const uint16_t 
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if ((threadIdx.x & 63) == 0 && acc != 0) atomicAdd(out, (unsigned long long)acc);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t t = part[0] + part[1] + part[2] + part[3];
+        if (t != 0) atomicAdd(out, (unsigned long long)t);
+    }
 }
 
 template <typename T>
 hipError_t launch_digest(const T *f, const uint16_t *cell, const uint8_t *types, int nx,
                          int ny, int pitch, size_t plane, unsigned long long *out,
                          hipStream_t s) {
-    hipLaunchKernelGGL(digest_kernel<T>, grid_cells(nx, ny), dim3(64, 4), 0, s, f, cell, types,
-                       nx, ny, pitch, plane, out);
+    const uint64_t N = (uint64_t)nx * (uint64_t)ny;
+    const unsigned blocks = (unsigned)std::min<uint64_t>(2048, (N + 255) / 256);
+    hipLaunchKernelGGL(digest_kernel<T>, dim3(blocks), dim3(256), 0, s, f, cell, types, nx, ny,
+                       pitch, plane, out);
     return hipGetLastError();
 }
 template hipError_t launch_digest<double>(const double *, const uint16_t *, const uint8_t *,

@@ -80,6 +80,7 @@ struct lbm_server {
     // worker-owned
     std::vector<Session> active;
     std::map<int, Group> groups;
+    std::map<int, std::pair<int32_t, int32_t>> tuned;  // precision -> (variant, order)
     size_t used = 0;
     std::thread worker;
 
@@ -167,6 +168,24 @@ struct lbm_server {
         st.busy_seconds += dt;
     }
 
+    // Batch configuration: the configured one, else the autotuner's choice,
+    // measured once per precision on the first batch of at least 8 members
+    // (its trials restore every member's state); smaller batches before
+    // that run one step per launch.
+    int configure_batch(int precision, lbm_batch *b, int32_t members) {
+        if (cfg.variant >= 0) return lbm_batch_configure(b, cfg.variant, cfg.order);
+        auto it = tuned.find(precision);
+        if (it != tuned.end()) return lbm_batch_configure(b, it->second.first, it->second.second);
+        if (members >= 8) {
+            int32_t v = 0, o = 0;
+            const int rc = lbm_batch_tune(b, cfg.quantum, &v, &o, nullptr, 0);
+            if (rc != LBM_OK) return rc;
+            tuned[precision] = {v, o};
+            return LBM_OK;
+        }
+        return lbm_batch_configure(b, lbm_tb_variant_count(precision), cfg.order);
+    }
+
     void round() {
         const double t0 = now_seconds();
         int64_t q = cfg.quantum;
@@ -195,10 +214,7 @@ struct lbm_server {
                 g.members = kv.second;
                 rc = lbm_batch_create(g.members.data(), (int32_t)g.members.size(), stream, &g.b);
                 if (rc == LBM_OK) rc = lbm_batch_set_graphs(g.b, 0);
-                if (rc == LBM_OK && cfg.variant >= 0)
-                    rc = lbm_batch_configure(g.b, cfg.variant, cfg.order);
-                else if (rc == LBM_OK)
-                    rc = lbm_batch_configure(g.b, lbm_tb_variant_count(kv.first), cfg.order);
+                if (rc == LBM_OK) rc = configure_batch(kv.first, g.b, (int32_t)g.members.size());
             }
             if (rc == LBM_OK) rc = lbm_batch_run(g.b, q, nullptr);
             int64_t ns = 0;
