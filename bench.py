@@ -39,17 +39,17 @@ HBM_PEAK_GBS = 8000.0
 # else and must be re-measured whenever the kernel changes.
 MEASURED_TRAFFIC_PER_STEP = {
     # shape 1 (32x64 dense regions, 8 steps per launch), 234 active tiles
-    ("distributor-1024x512-L3", "f32", 1): 14.891e6 / 8,
+    ("distributor-1024x512-L3", "f32", 1): 14.886e6 / 8,
     # shape 0 (32x64 compacted regions)
-    ("distributor-1024x512-L3", "f32", 0): 14.950e6 / 8,
+    ("distributor-1024x512-L3", "f32", 0): 14.928e6 / 8,
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
 MEASURED_TRAFFIC_PER_LAUNCH = {
     # profiles/sweep_batch_float_batch-256-candidates.txt; shapes 0..3 temporal
     # blocking (0: 32x64 compacted, 3: 16x64 compacted), 4 = one step per launch
-    ("batch-256-candidates", "f32", 3, 1): 700.878e6,
-    ("batch-256-candidates", "f32", 3, 0): 1366.025e6,
+    ("batch-256-candidates", "f32", 3, 1): 700.881e6,
+    ("batch-256-candidates", "f32", 3, 0): 1366.030e6,
     ("batch-256-candidates", "f32", 0, 1): 709.182e6,
     ("batch-256-candidates", "f32", 0, 0): 1556.398e6,
     ("batch-256-candidates", "f32", 4, 1): 684.539e6,

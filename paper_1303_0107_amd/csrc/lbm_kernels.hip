@@ -95,6 +95,16 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid,
 // on a mirror-symmetric lattice the computed flow is mirror-symmetric bit for
 // bit.  Multiply-adds are fused only inside one expression, as written, so
 // every kernel that inlines this function rounds identically.
+// Reciprocal for the per-cell arithmetic: in float the hardware reciprocal
+// refined by one Newton step, r + r (1 - x r) (the raw estimate's error has
+// a sign bias that the flux split between outlets integrates); in double
+// the division.  The same in every kernel.
+__device__ __forceinline__ float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename Storage, typename Arith, typename Poly>
 struct OffsetCell {
     using T = Storage;
@@ -113,7 +123,7 @@ struct OffsetCell {
         const CT dr = ((d[0] + (d[1] + d[3])) + (d[2] + d[4])) + ((d[5] + d[8]) + (d[6] + d[7]));
         const CT jx = (d[1] + (d[5] + d[8])) - (d[3] + (d[6] + d[7]));
         const CT jy = (d[2] + (d[5] + d[6])) - (d[4] + (d[8] + d[7]));
-        const CT ir = CT(1) / (CT(1) + dr);
+        const CT ir = recip(CT(1) + dr);
         ux = jx * ir;
         uy = jy * ir;
     }
@@ -125,7 +135,7 @@ struct OffsetCell {
 #pragma clang fp contract(on)
         if (type == kInlet) {
             const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[3] + (d[6] + d[7]));
-            const CT dr = (s + bx) / (CT(1) - bx);
+            const CT dr = (s + bx) * recip(CT(1) - bx);
             const CT ru = (CT(1) + dr) * bx;
             const CT h = CT(0.5) * (d[2] - d[4]);
             d[1] = d[3] + (CT(2) / CT(3)) * ru;
@@ -133,7 +143,7 @@ struct OffsetCell {
             d[8] = d[6] + h + (CT(1) / CT(6)) * ru;
         } else if (type == kOutlet) {
             const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[1] + (d[5] + d[8]));
-            const CT uo = (s + (CT)a.one_minus_rho_out) / (CT)a.rho_out;
+            const CT uo = (s + (CT)a.one_minus_rho_out) * recip((CT)a.rho_out);
             const CT ru = (CT)a.rho_out * uo;
             const CT h = CT(0.5) * (d[2] - d[4]);
             d[3] = d[1] - (CT(2) / CT(3)) * ru;
@@ -142,7 +152,7 @@ struct OffsetCell {
         } else if (type == kOutletNeumann) {
             // rho = (1 + s) / (1 + ux): offsets of the Zou-He velocity closure
             const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[1] + (d[5] + d[8]));
-            const CT dr = (s - bx) / (CT(1) + bx);
+            const CT dr = (s - bx) * recip(CT(1) + bx);
             const CT ru = (CT(1) + dr) * bx, rv = (CT(1) + dr) * by;
             const CT h = CT(0.5) * (d[2] - d[4]);
             d[3] = d[1] - (CT(2) / CT(3)) * ru;
@@ -153,7 +163,7 @@ struct OffsetCell {
         const CT rho = CT(1) + dr;
         const CT jx = (d[1] + (d[5] + d[8])) - (d[3] + (d[6] + d[7]));
         const CT jy = (d[2] + (d[5] + d[6])) - (d[4] + (d[8] + d[7]));
-        const CT ir = CT(1) / rho;
+        const CT ir = recip(rho);
         const CT ux = jx * ir, uy = jy * ir;
         const CT om = (CT)a.omega;
         // Opposite directions i, opp(i) have c.u = +-cu: their equilibrium
