@@ -63,12 +63,22 @@ __device__ __forceinline__ h16 f32_to_h16_rne(float f) {
     return (h16)f;
 }
 
+// FP16 offsets are stored scaled by 2^12: |f - w| rarely exceeds 0.2, so the
+// scaled values stay far below binary16's largest finite value, and offsets
+// down to 1.5e-8 keep binary16's full 11-bit precision instead of falling into
+// its subnormal range (below 6.1e-5 unscaled).  Scaling by a power of two is
+// exact in float, so the only rounding is binary16's.
+constexpr float kH16Scale = 4096.0f, kH16Unscale = 1.0f / 4096.0f;
 template <>
 struct Sto<h16> {
-    __device__ static __forceinline__ double to_d(h16 v) { return (double)(float)v; }
-    __device__ static __forceinline__ h16 from_d(double v) { return f32_to_h16_rne((float)v); }
-    __device__ static __forceinline__ float to_f(h16 v) { return (float)v; }
-    __device__ static __forceinline__ h16 from_f(float v) { return f32_to_h16_rne(v); }
+    __device__ static __forceinline__ double to_d(h16 v) {
+        return (double)((float)v * kH16Unscale);
+    }
+    __device__ static __forceinline__ h16 from_d(double v) {
+        return f32_to_h16_rne((float)v * kH16Scale);
+    }
+    __device__ static __forceinline__ float to_f(h16 v) { return (float)v * kH16Unscale; }
+    __device__ static __forceinline__ h16 from_f(float v) { return f32_to_h16_rne(v * kH16Scale); }
 };
 template <>
 struct Sto<bf16> {

@@ -174,12 +174,16 @@ __global__ __launch_bounds__(256) void step_batch_kernel(
 
 // Temporal blocking.  Tile t = tiles[blockIdx.x] packs (tile row << 16 | tile
 // column); the tile's cells are [tx*IW, tx*IW+IW) x [ty*IH, ty*IH+IH).
-// Lane l of wave w owns region cells (l, w + c*NW), c = 0..CPT-1.
-// PP (ping-pong): two LDS copies of the region, each step reads one and
-// writes the other (one barrier per step, nothing held in registers across
-// the barrier).  Otherwise one copy updated in place: every thread keeps its
-// cells' new populations in registers until all reads of the step are done.
-template <class Cell, int RH, int H, int NT, bool PP, bool CHECK, bool BC>
+// Lane l of wave w owns region cells (l, w + c*NW), c = 0..CPT-1.  Two LDS
+// copies of the region, interleaved by plane (plane i of copy b at index
+// (2i + b) * PL): each step reads one copy and writes the other, with one
+// barrier per step.  The step loop is unrolled by two so that the copy is a
+// compile-time constant; each pull then reads a per-cell LDS byte address,
+// computed once per launch, plus an immediate offset.  A cell's depth (its
+// distance to the region edge; 0 for solid cells) bounds the steps it can
+// take: it is advanced at step s exactly when depth >= s, and is a tile cell
+// exactly when depth >= H.
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC>
 __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, const int t,
                                         const int steps, double *part_out) {
     using T = typename Cell::T;
@@ -187,6 +191,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
     constexpr int RW = 64, IW = RW - 2 * H, IH = RH - 2 * H;
     constexpr int NW = NT / 64, CPT = RH / NW, PL = RW * RH;
     static_assert(RH % NW == 0, "region rows must split evenly over waves");
+    static_assert((size_t)PL * sizeof(T) < 65536, "copy offset must fit an LDS immediate");
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *L = reinterpret_cast<T *>(lds_raw);
 
@@ -196,89 +201,97 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
     const bool col_in = gx >= 0 && gx < a.nx;
 
     uint32_t cw[CPT];
-    UinT<T> uin[CPT];  // inlet velocity of the thread's cells, read once per launch
+    int depth[CPT];
+    const T *src[CPT][9];  // LDS address of each pull in copy 0
+    UinT<T> uin[CPT];      // inlet velocity of the thread's cells, read once per launch
+    T v[CPT][9];
+    size_t n[CPT];
+    // The cell words of all the thread's cells are read first, then all their
+    // populations, before the first LDS store, so that the HBM latencies
+    // overlap; solid cells are not read.
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int gy = oy + wave + c * NW;
+        const bool in = col_in && gy >= 0 && gy < a.ny;
+        n[c] = in ? (size_t)gy * a.pitch + gx : 0;
+        cw[c] = in ? a.cell[n[c]] : 0u;
+    }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int ry = wave + c * NW, gy = oy + ry;
-        const bool in = col_in && gy >= 0 && gy < a.ny;
-        const size_t n = in ? (size_t)gy * a.pitch + gx : 0;
-        cw[c] = in ? a.cell[n] : 0u;
-        const bool live = in && cell_type(cw[c]) != kSolid;
-        uin[c] = (in && cell_type(cw[c]) == kInlet) ? a.uin[gy] : UinT<T>(0);
+        const bool live = cell_type(cw[c]) != kSolid;  // cells off the lattice read as solid
+        depth[c] = live ? min(min(lane, RW - 1 - lane), min(ry, RH - 1 - ry)) : 0;
+        uin[c] = cell_type(cw[c]) == kInlet ? a.uin[gy] : UinT<T>(0);
+        if (live) {
+            const T *p = a.fin + n[c];
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-            L[i * PL + ry * RW + lane] = live ? a.fin[(size_t)i * a.plane + n] : Cell::store(CT(0));
+            for (int i = 0; i < 9; ++i) v[c][i] = p[(size_t)i * a.plane];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[c][i] = Cell::store(CT(0));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int pos = (wave + c * NW) * RW + lane;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            L[2 * i * PL + pos] = v[c][i];
+            const bool wall = i > 0 && ((cw[c] >> (i - 1)) & 1u);
+            const int e = wall ? 2 * kOpp[i] * PL + pos : 2 * i * PL + pos - kCy[i] * RW - kCx[i];
+            src[c][i] = L + e;
+        }
     }
     __syncthreads();
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
-    int src_buf = 0;
-    for (int s = 1; s <= steps; ++s) {
+    // One step reading copy B and writing copy 1 - B; true when it was the last.
+    auto step = [&](auto copy, const int s) -> bool {
+        constexpr int B = decltype(copy)::value;
         const bool last = s == steps;
-        const T *Ls = L + (PP ? src_buf * 9 * PL : 0);
-        T *Ld = L + (PP ? (1 - src_buf) * 9 * PL : 0);
-        T out[PP ? 1 : CPT][9];
-        bool upd[CPT];
+        const int need = last ? H : s;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int ry = wave + c * NW;
+            if (depth[c] < need) continue;
+            const int ry = wave + c * NW, gy = oy + ry, pos = ry * RW + lane;
             const uint32_t type = update_type(cw[c]);
-            bool v = type != kSolid && lane >= s && lane < RW - s && ry >= s && ry < RH - s;
-            if (last) v = v && lane >= H && lane < H + IW && ry >= H && ry < H + IH;
-            upd[c] = v;
-            if (v) {
-                const int gy = oy + ry;
-                CT bx = type == kInlet ? (CT)uin[c] : CT(0), by = CT(0);
-                if (BC && type == kOutletNeumann && (cw[c] & kWordLeftLive)) {
-                    CT g[9];
+            CT bx = type == kInlet ? (CT)uin[c] : CT(0), by = CT(0);
+            if (BC && type == kOutletNeumann && (cw[c] & kWordLeftLive)) {
+                CT g[9];
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) g[i] = Cell::load(Ls[i * PL + ry * RW + lane - 1]);
-                    Cell::velocity(g, bx, by);
-                }
-                CT f[9];
-                if (BC && (cw[c] & kWordGeneral)) {
+                for (int i = 0; i < 9; ++i) g[i] = Cell::load(L[(2 * i + B) * PL + pos - 1]);
+                Cell::velocity(g, bx, by);
+            }
+            CT f[9];
+            if (BC && (cw[c] & kWordGeneral)) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        f[i] = Cell::load(Ls[general_src(cw[c], i, lane, ry, gy, a.ny, a.flags,
-                                                         PL, RW)]);
-                } else {
+                for (int i = 0; i < 9; ++i)
+                    f[i] = Cell::load(
+                        L[general_src(cw[c], i, lane, ry, gy, a.ny, a.flags, 2 * PL, RW) + B * PL]);
+            } else {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        const bool wall = i > 0 && ((cw[c] >> (i - 1)) & 1u);
-                        const int src = wall ? kOpp[i] * PL + ry * RW + lane
-                                             : i * PL + (ry - kCy[i]) * RW + lane - kCx[i];
-                        f[i] = Cell::load(Ls[src]);
-                    }
-                }
-                double mass, ux, uy;
-                Cell::update(f, type, bx, by, a, mass, ux, uy);
-                if (last) {
-                    const size_t n = (size_t)gy * a.pitch + gx;
+                for (int i = 0; i < 9; ++i)
+                    f[i] = Cell::load(src[c][i][B * PL]);
+            }
+            double mass, ux, uy;
+            Cell::update(f, type, bx, by, a, mass, ux, uy);
+            if (last) {
+                const size_t n = (size_t)gy * a.pitch + gx;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) a.fout[(size_t)i * a.plane + n] = Cell::store(f[i]);
-                    if (CHECK) check_terms(a, n, mass, ux, uy, part);
-                } else if (PP) {
+                for (int i = 0; i < 9; ++i) a.fout[(size_t)i * a.plane + n] = Cell::store(f[i]);
+                if (CHECK) check_terms(a, n, mass, ux, uy, part);
+            } else {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) Ld[i * PL + ry * RW + lane] = Cell::store(f[i]);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) out[PP ? 0 : c][i] = Cell::store(f[i]);
-                }
+                for (int i = 0; i < 9; ++i) L[(2 * i + 1 - B) * PL + pos] = Cell::store(f[i]);
             }
         }
-        if (last) break;
-        if (!PP) {
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < CPT; ++c)
-                if (upd[c]) {
-                    const int ry = wave + c * NW;
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) L[i * PL + ry * RW + lane] = out[PP ? 0 : c][i];
-                }
-        }
+        if (last) return true;
         __syncthreads();
-        src_buf = 1 - src_buf;
+        return false;
+    };
+    for (int s = 1; s <= steps; s += 2) {
+        if (step(std::integral_constant<int, 0>{}, s)) break;
+        if (step(std::integral_constant<int, 1>{}, s + 1)) break;
     }
     if (CHECK) {
         block_sum<4, NT>(part);
@@ -324,16 +337,34 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
 
     int cls[CPT];
     uint32_t cw[CPT];
+    size_t n[CPT];
+    T v[CPT][9];
+    // Cell words first, then populations, then the LDS stores, so that the
+    // HBM latencies overlap; solid cells are not read.
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const int ry = wave + c * NW, gy = oy + ry;
+        const int gy = oy + wave + c * NW;
         const bool in = col_in && gy >= 0 && gy < a.ny;
-        const size_t n = in ? (size_t)gy * a.pitch + gx : 0;
-        cw[c] = in ? a.cell[n] : 0u;
-        const bool live = in && cell_type(cw[c]) != kSolid;
+        n[c] = in ? (size_t)gy * a.pitch + gx : 0;
+        cw[c] = in ? a.cell[n[c]] : 0u;
+    }
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-            L[i * PL + ry * RW + lane] = live ? a.fin[(size_t)i * a.plane + n] : Cell::store(CT(0));
+    for (int c = 0; c < CPT; ++c) {
+        if (cell_type(cw[c]) != kSolid) {  // cells off the lattice read as solid
+            const T *p = a.fin + n[c];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[c][i] = p[(size_t)i * a.plane];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[c][i] = Cell::store(CT(0));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int ry = wave + c * NW;
+        const bool live = cell_type(cw[c]) != kSolid;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i * PL + ry * RW + lane] = v[c][i];
         const int depth = min(min(lane, RW - 1 - lane), min(ry, RH - 1 - ry));
         cls[c] = live ? min(depth, H) : 0;
 #pragma unroll
@@ -451,40 +482,40 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
 }
 
 // One region shape: rows x 64 cells, halo H, dense or compacted.
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, bool COMPACT, bool CHECK, bool BC>
 __device__ __forceinline__ void tb_dispatch(const SweepArgs<typename Cell::T> &a, const int t,
                                             const int steps, double *part_out) {
     if constexpr (COMPACT)
         tb_body_compact<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
     else
-        tb_body<Cell, RH, H, NT, PP, CHECK, BC>(a, t, steps, part_out);
+        tb_body<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
 }
 
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, bool COMPACT, bool CHECK, bool BC>
 __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
                                                 const int32_t *__restrict__ tiles,
                                                 int steps) {
-    tb_dispatch<Cell, RH, H, NT, PP, COMPACT, CHECK, BC>(
+    tb_dispatch<Cell, RH, H, NT, COMPACT, CHECK, BC>(
         a, tiles[blockIdx.x], steps, CHECK ? a.partials + (size_t)blockIdx.x * 4 : nullptr);
 }
 
 // Many lattices in one launch: work item b is tile tiles[b] of lattice
 // lat[b], whose arguments are args[lat[b]]; lat[b] < 0 marks a padding item
 // (the whole workgroup leaves at once, before any barrier).
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool BC>
+template <class Cell, int RH, int H, int NT, bool COMPACT, bool BC>
 __global__ __launch_bounds__(NT) void tb_batch_kernel(
     const SweepArgs<typename Cell::T> *__restrict__ args, const int32_t *__restrict__ lat,
     const int32_t *__restrict__ tiles, int steps) {
     const int l = lat[blockIdx.x];
     if (l < 0) return;
     const SweepArgs<typename Cell::T> a = args[l];
-    tb_dispatch<Cell, RH, H, NT, PP, COMPACT, false, BC>(a, tiles[blockIdx.x], steps, nullptr);
+    tb_dispatch<Cell, RH, H, NT, COMPACT, false, BC>(a, tiles[blockIdx.x], steps, nullptr);
 }
 
 // Dynamic LDS of one region shape.
-template <typename T, int RH, bool PP, bool COMPACT>
+template <typename T, int RH, bool COMPACT>
 constexpr size_t tb_lds_bytes() {
-    return (size_t)((PP || COMPACT) ? 2 : 1) * 9 * 64 * RH * sizeof(T) +
+    return (size_t)2 * 9 * 64 * RH * sizeof(T) +
            (COMPACT ? (size_t)64 * RH * sizeof(uint32_t) : 0);
 }
 
@@ -512,11 +543,11 @@ inline hipError_t set_lds(const void *k, size_t lds, bool &done) {
     return e;
 }
 
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, bool COMPACT, bool CHECK, bool BC>
 hipError_t launch_tb_one(const SweepArgs<typename Cell::T> &a, const int32_t *tiles, int n_tiles,
                          int steps, hipStream_t s) {
-    const size_t lds = tb_lds_bytes<typename Cell::T, RH, PP, COMPACT>();
-    auto k = tb_kernel<Cell, RH, H, NT, PP, COMPACT, CHECK, BC>;
+    const size_t lds = tb_lds_bytes<typename Cell::T, RH, COMPACT>();
+    auto k = tb_kernel<Cell, RH, H, NT, COMPACT, CHECK, BC>;
     static bool configured = false;  // one flag per kernel instantiation
     const hipError_t e = set_lds((const void *)k, lds, configured);
     if (e != hipSuccess) return e;
@@ -524,26 +555,26 @@ hipError_t launch_tb_one(const SweepArgs<typename Cell::T> &a, const int32_t *ti
     return hipGetLastError();
 }
 
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT>
+template <class Cell, int RH, int H, int NT, bool COMPACT>
 hipError_t launch_tb(const SweepArgs<typename Cell::T> &a, const int32_t *tiles, int n_tiles,
                      int steps, bool check, hipStream_t s) {
     if (n_tiles <= 0 || steps <= 0) return hipSuccess;
     if (steps > H) return hipErrorInvalidValue;
     const bool bc = a.flags != 0;
     if (check && bc)
-        return launch_tb_one<Cell, RH, H, NT, PP, COMPACT, true, true>(a, tiles, n_tiles, steps, s);
+        return launch_tb_one<Cell, RH, H, NT, COMPACT, true, true>(a, tiles, n_tiles, steps, s);
     if (check)
-        return launch_tb_one<Cell, RH, H, NT, PP, COMPACT, true, false>(a, tiles, n_tiles, steps, s);
+        return launch_tb_one<Cell, RH, H, NT, COMPACT, true, false>(a, tiles, n_tiles, steps, s);
     if (bc)
-        return launch_tb_one<Cell, RH, H, NT, PP, COMPACT, false, true>(a, tiles, n_tiles, steps, s);
-    return launch_tb_one<Cell, RH, H, NT, PP, COMPACT, false, false>(a, tiles, n_tiles, steps, s);
+        return launch_tb_one<Cell, RH, H, NT, COMPACT, false, true>(a, tiles, n_tiles, steps, s);
+    return launch_tb_one<Cell, RH, H, NT, COMPACT, false, false>(a, tiles, n_tiles, steps, s);
 }
 
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT, bool BC>
+template <class Cell, int RH, int H, int NT, bool COMPACT, bool BC>
 hipError_t launch_tb_batch_one(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
                                const int32_t *tiles, int n_items, int steps, hipStream_t s) {
-    const size_t lds = tb_lds_bytes<typename Cell::T, RH, PP, COMPACT>();
-    auto k = tb_batch_kernel<Cell, RH, H, NT, PP, COMPACT, BC>;
+    const size_t lds = tb_lds_bytes<typename Cell::T, RH, COMPACT>();
+    auto k = tb_batch_kernel<Cell, RH, H, NT, COMPACT, BC>;
     static bool configured = false;  // one flag per kernel instantiation; set also on an
                                      // empty call, so that it can precede a graph capture
     const hipError_t e = set_lds((const void *)k, lds, configured);
@@ -553,14 +584,14 @@ hipError_t launch_tb_batch_one(const SweepArgs<typename Cell::T> *args, const in
     return hipGetLastError();
 }
 
-template <class Cell, int RH, int H, int NT, bool PP, bool COMPACT>
+template <class Cell, int RH, int H, int NT, bool COMPACT>
 hipError_t launch_tb_batch(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
                            const int32_t *tiles, int n_items, int steps, bool bc, hipStream_t s) {
     if (steps > H) return hipErrorInvalidValue;
     if (bc)
-        return launch_tb_batch_one<Cell, RH, H, NT, PP, COMPACT, true>(args, lat, tiles, n_items,
+        return launch_tb_batch_one<Cell, RH, H, NT, COMPACT, true>(args, lat, tiles, n_items,
                                                                        steps, s);
-    return launch_tb_batch_one<Cell, RH, H, NT, PP, COMPACT, false>(args, lat, tiles, n_items,
+    return launch_tb_batch_one<Cell, RH, H, NT, COMPACT, false>(args, lat, tiles, n_items,
                                                                     steps, s);
 }
 
@@ -585,7 +616,7 @@ hipError_t launch_tb_variant(const SweepArgs<typename Cell::T> &a, const int32_t
     if constexpr (V < TbVariants<T>::count) {
         if (variant == V)
             return launch_tb<Cell, TbVariants<T>::v[V].rows, TbVariants<T>::v[V].halo,
-                             kTbThreads, true, TbVariants<T>::v[V].compact>(a, tiles, n_tiles,
+                             kTbThreads, TbVariants<T>::v[V].compact>(a, tiles, n_tiles,
                                                                             steps, check, s);
         return launch_tb_variant<Cell, V + 1>(a, tiles, n_tiles, steps, check, variant, s);
     } else {
@@ -601,7 +632,7 @@ hipError_t launch_tb_batch_variant(const SweepArgs<typename Cell::T> *args, cons
     if constexpr (V < TbVariants<T>::count) {
         if (variant == V)
             return launch_tb_batch<Cell, TbVariants<T>::v[V].rows, TbVariants<T>::v[V].halo,
-                                   kTbThreads, true, TbVariants<T>::v[V].compact>(
+                                   kTbThreads, TbVariants<T>::v[V].compact>(
                 args, lat, tiles, n_items, steps, bc, s);
         return launch_tb_batch_variant<Cell, V + 1>(args, lat, tiles, n_items, steps, variant,
                                                     bc, s);
