@@ -312,7 +312,8 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
 // step the cells to update are a prefix of the list, and consecutive lanes
 // take consecutive entries.  Within a class, entries keep row-major order.
 // Each update reads the same nine values as the dense form, so the results
-// are the same bits.  LDS: the two region copies, then PL list words.
+// are the same bits.  LDS: the two region copies, interleaved by plane as in
+// the dense form, then PL list words.
 template <class Cell, int RH, int H, int NT, bool CHECK, bool BC>
 __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T> &a, const int t,
                                                 const int steps, double *part_out) {
@@ -364,7 +365,7 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
         const int ry = wave + c * NW;
         const bool live = cell_type(cw[c]) != kSolid;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) L[i * PL + ry * RW + lane] = v[c][i];
+        for (int i = 0; i < 9; ++i) L[2 * i * PL + ry * RW + lane] = v[c][i];
         const int depth = min(min(lane, RW - 1 - lane), min(ry, RH - 1 - ry));
         cls[c] = live ? min(depth, H) : 0;
 #pragma unroll
@@ -409,68 +410,74 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
     __syncthreads();
     const int n_all = cls_base[0];
     uint32_t ent[CPT];
-    UinT<T> uin[CPT];  // inlet velocity of the thread's entries, read once per launch
+    const T *src[CPT][9];  // LDS address of each pull of the thread's entries in copy 0
+    UinT<T> uin[CPT];      // inlet velocity of the thread's entries, read once per launch
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
         const int j = threadIdx.x + m * NT;
         ent[m] = j < n_all ? list[j] : 0u;
-        const bool inlet = j < n_all && cell_type(ent[m] >> 16) == kInlet;
-        uin[m] = inlet ? a.uin[oy + (int)(ent[m] & 0xffffu) / RW] : UinT<T>(0);
+        const uint32_t c = ent[m] >> 16;
+        const int pos = (int)(ent[m] & 0xffffu);
+        uin[m] = (j < n_all && cell_type(c) == kInlet) ? a.uin[oy + pos / RW] : UinT<T>(0);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const bool wall = i > 0 && ((c >> (i - 1)) & 1u);
+            const int e = wall ? 2 * kOpp[i] * PL + pos : 2 * i * PL + pos - kCy[i] * RW - kCx[i];
+            src[m][i] = L + e;
+        }
     }
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
-    int src_buf = 0;
-    for (int s = 1; s <= steps; ++s) {
+    // One step reading copy B and writing copy 1 - B; true when it was the last.
+    auto step = [&](auto copy, const int s) -> bool {
+        constexpr int B = decltype(copy)::value;
         const bool last = s == steps;
         // cells of class >= s, or the tile cells (class H) at the last step
-        const int n_s = last ? cls_base[H - 1 + 1] + cls_total[H] : cls_base[s] + cls_total[s];
-        const T *Ls = L + src_buf * 9 * PL;
-        T *Ld = L + (1 - src_buf) * 9 * PL;
+        const int n_s = last ? cls_base[H] + cls_total[H] : cls_base[s] + cls_total[s];
 #pragma unroll
         for (int m = 0; m < CPT; ++m) {
-            if (threadIdx.x + m * NT < n_s) {
-                const uint32_t e = ent[m];
-                const uint32_t c = e >> 16;
-                const int pos = (int)(e & 0xffffu);
-                const int ry = pos / RW, lx = pos % RW;
-                const uint32_t type = update_type(c);
-                const int gy = oy + ry;
-                CT bx = type == kInlet ? (CT)uin[m] : CT(0), by = CT(0);
-                if (BC && type == kOutletNeumann && (c & kWordLeftLive)) {
-                    CT g[9];
+            if (threadIdx.x + m * NT >= n_s) continue;
+            const uint32_t c = ent[m] >> 16;
+            const int pos = (int)(ent[m] & 0xffffu);
+            const int ry = pos / RW, lx = pos % RW;
+            const uint32_t type = update_type(c);
+            const int gy = oy + ry;
+            CT bx = type == kInlet ? (CT)uin[m] : CT(0), by = CT(0);
+            if (BC && type == kOutletNeumann && (c & kWordLeftLive)) {
+                CT g[9];
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) g[i] = Cell::load(Ls[i * PL + pos - 1]);
-                    Cell::velocity(g, bx, by);
-                }
-                CT f[9];
-                if (BC && (c & kWordGeneral)) {
+                for (int i = 0; i < 9; ++i) g[i] = Cell::load(L[(2 * i + B) * PL + pos - 1]);
+                Cell::velocity(g, bx, by);
+            }
+            CT f[9];
+            if (BC && (c & kWordGeneral)) {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i)
-                        f[i] = Cell::load(Ls[general_src(c, i, lx, ry, gy, a.ny, a.flags, PL, RW)]);
-                } else {
+                for (int i = 0; i < 9; ++i)
+                    f[i] = Cell::load(
+                        L[general_src(c, i, lx, ry, gy, a.ny, a.flags, 2 * PL, RW) + B * PL]);
+            } else {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) {
-                        const bool wall = i > 0 && ((c >> (i - 1)) & 1u);
-                        const int src = wall ? kOpp[i] * PL + pos : i * PL + pos - kCy[i] * RW - kCx[i];
-                        f[i] = Cell::load(Ls[src]);
-                    }
-                }
-                double mass, ux, uy;
-                Cell::update(f, type, bx, by, a, mass, ux, uy);
-                if (last) {
-                    const size_t n = (size_t)gy * a.pitch + (ox + lx);
+                for (int i = 0; i < 9; ++i) f[i] = Cell::load(src[m][i][B * PL]);
+            }
+            double mass, ux, uy;
+            Cell::update(f, type, bx, by, a, mass, ux, uy);
+            if (last) {
+                const size_t n = (size_t)gy * a.pitch + (ox + lx);
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) a.fout[(size_t)i * a.plane + n] = Cell::store(f[i]);
-                    if (CHECK) check_terms(a, n, mass, ux, uy, part);
-                } else {
+                for (int i = 0; i < 9; ++i) a.fout[(size_t)i * a.plane + n] = Cell::store(f[i]);
+                if (CHECK) check_terms(a, n, mass, ux, uy, part);
+            } else {
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) Ld[i * PL + pos] = Cell::store(f[i]);
-                }
+                for (int i = 0; i < 9; ++i) L[(2 * i + 1 - B) * PL + pos] = Cell::store(f[i]);
             }
         }
-        if (last) break;
+        if (last) return true;
         __syncthreads();
-        src_buf = 1 - src_buf;
+        return false;
+    };
+    for (int s = 1; s <= steps; s += 2) {
+        if (step(std::integral_constant<int, 0>{}, s)) break;
+        if (step(std::integral_constant<int, 1>{}, s + 1)) break;
     }
     if (CHECK) {
         block_sum<4, NT>(part);
