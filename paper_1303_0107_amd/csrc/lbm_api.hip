@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -40,11 +42,106 @@ struct HipFail {
         if (e_ != hipSuccess) throw HipFail{e_, #expr};       \
     } while (0)
 
+// Recycled allocations.  hipMalloc and hipFree (and their pinned-host
+// counterparts) cost tens of microseconds each, and a server creates and
+// destroys a lattice's buffers for every request.  A destroyed handle, whose
+// stream has been synchronised first, hands its blocks to this cache, and
+// allocations take a cached block of their size class on the same device.
+// Sizes are rounded up to a multiple of 1/8 of their power of two (at most
+// 12.5 % slack).  At most `cap` bytes wait; the oldest blocks are freed first.
+class BlockCache {
+  public:
+    BlockCache(bool host, size_t cap) : host_(host), cap_(cap) {}
+    static size_t size_class(size_t n) {
+        if (n <= 4096) return (n + 255) / 256 * 256;
+        size_t p = 4096;
+        while (p * 2 <= n) p *= 2;
+        const size_t step = p / 8;
+        return (n + step - 1) / step * step;
+    }
+    // A block of exactly `cls` bytes on `dev` (-1 for host), or nullptr.
+    void *take(int dev, size_t cls) {
+        std::lock_guard<std::mutex> g(m_);
+        for (auto it = blocks_.begin(); it != blocks_.end(); ++it)
+            if (it->dev == dev && it->cls == cls) {
+                void *p = it->p;
+                total_ -= cls;
+                blocks_.erase(it);
+                return p;
+            }
+        return nullptr;
+    }
+    void give(int dev, size_t cls, void *p) {
+        std::lock_guard<std::mutex> g(m_);
+        blocks_.push_back({dev, cls, p});
+        total_ += cls;
+        while (total_ > cap_ && !blocks_.empty()) {
+            const Block b = blocks_.front();
+            blocks_.pop_front();
+            total_ -= b.cls;
+            release(b);
+        }
+    }
+
+  private:
+    struct Block {
+        int dev;
+        size_t cls;
+        void *p;
+    };
+    void release(const Block &b) {
+        if (host_) {
+            (void)hipHostFree(b.p);
+        } else {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice(b.dev);
+            (void)hipFree(b.p);
+            (void)hipSetDevice(cur);
+        }
+    }
+    bool host_;
+    size_t cap_;
+    std::mutex m_;
+    std::deque<Block> blocks_;
+    size_t total_ = 0;
+};
+// Never destroyed: blocks cached at process exit are left to the runtime.
+BlockCache &device_cache() {
+    static BlockCache *c = new BlockCache(false, (size_t)4 << 30);
+    return *c;
+}
+BlockCache &host_cache() {
+    static BlockCache *c = new BlockCache(true, (size_t)64 << 20);
+    return *c;
+}
+
+// Pinned host memory of at least `bytes`, from the cache when possible;
+// `got` receives the size class actually held.
+void *pinned_alloc(size_t bytes, size_t &got) {
+    got = BlockCache::size_class(bytes);
+    if (void *p = host_cache().take(-1, got)) return p;
+    void *p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, got, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw std::bad_alloc();
+    }
+    return p;
+}
+
 struct DeviceBuffer {
     void *p = nullptr;
     size_t bytes = 0;
+    int dev = 0;
     void reset() {
         if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Hand the block to the cache; only when no queued work still uses it.
+    void recycle() {
+        if (p) device_cache().give(dev, bytes, p);
         p = nullptr;
         bytes = 0;
     }
@@ -53,13 +150,18 @@ struct DeviceBuffer {
         if (bytes >= n) return;
         reset();
         if (n == 0) return;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            throw std::bad_alloc();
+        const size_t cls = BlockCache::size_class(n);
+        (void)hipGetDevice(&dev);
+        p = device_cache().take(dev, cls);
+        if (!p) {
+            hipError_t e = hipMalloc(&p, cls);
+            if (e != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                throw std::bad_alloc();
+            }
         }
-        bytes = n;
+        bytes = cls;
     }
     template <typename U>
     U *as() const {
@@ -278,6 +380,21 @@ struct lbm_handle {
         for (Graph &g : graphs) (void)hipGraphExecDestroy(g.exec);
         graphs.clear();
     }
+    // Hand every device block and both pinned staging areas to the caches;
+    // the caller has synchronised the stream.
+    void recycle() {
+        DeviceBuffer *bufs[] = {&f[0], &f[1], &cell, &types, &uin, &uprev, &partials,
+                                &red, &out_rows, &bnd, &macro, &cand, &sel, &select_tmp,
+                                &removed_rho, &tiles};
+        for (DeviceBuffer *b : bufs) b->recycle();
+        if (pinned) host_cache().give(-1, pinned_bytes, pinned);
+        pinned = nullptr;
+        pinned_bytes = 0;
+        if (tile_copied) (void)hipEventSynchronize(tile_copied);
+        if (tile_pinned) host_cache().give(-1, tile_pinned_count * sizeof(int32_t), tile_pinned);
+        tile_pinned = nullptr;
+        tile_pinned_count = 0;
+    }
     ~lbm_handle() {
         drop_graphs();
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -323,15 +440,17 @@ size_t footprint(int nx, int ny, int precision) {
     const int pitch = pitch_for(nx);
     const size_t plane = (size_t)ny * pitch, N = (size_t)nx * ny;
     const size_t es = elem_size(precision);
-    size_t b = 2 * 9 * plane * es;           // populations
-    b += plane * sizeof(uint16_t);           // cell words
-    b += N;                                  // type map
-    b += (size_t)ny * sizeof(double);        // inlet profile
-    b += 2 * plane * sizeof(double);         // u_prev
+    // each buffer is allocated in its size class
+    auto c = [](size_t n) { return BlockCache::size_class(n); };
+    size_t b = 2 * c(9 * plane * es);        // populations
+    b += c(plane * sizeof(uint16_t));        // cell words
+    b += c(N);                               // type map
+    b += c((size_t)ny * sizeof(double));     // inlet profile
+    b += c(2 * plane * sizeof(double));      // u_prev
     const size_t ntiles = max_tile_count(nx, ny, precision);
-    b += std::max((size_t)sweep_blocks(nx, ny), ntiles) * 4 * sizeof(double);
-    b += ntiles * sizeof(int32_t);
-    b += 3 * N * sizeof(double);             // macro field (exchange step)
+    b += c(std::max((size_t)sweep_blocks(nx, ny), ntiles) * 4 * sizeof(double));
+    b += c(ntiles * sizeof(int32_t));
+    b += c(3 * N * sizeof(double));          // macro field (exchange step)
     return b;
 }
 
@@ -414,10 +533,9 @@ void rebuild_tiles(lbm_handle *h) {
         if (h->tile_pinned) (void)hipHostFree(h->tile_pinned);
         h->tile_pinned = nullptr;
         h->tile_pinned_count = 0;
-        void *p = nullptr;
-        HIP_TRY(hipHostMalloc(&p, cap * sizeof(int32_t), hipHostMallocDefault));
-        h->tile_pinned = static_cast<int32_t *>(p);
-        h->tile_pinned_count = cap;
+        size_t got = 0;
+        h->tile_pinned = static_cast<int32_t *>(pinned_alloc(cap * sizeof(int32_t), got));
+        h->tile_pinned_count = got / sizeof(int32_t);
     }
     if (h->n_tiles > 0) {
         std::memcpy(h->tile_pinned, h->tile_host.data(), h->n_tiles * sizeof(int32_t));
@@ -459,10 +577,9 @@ void ensure_pinned(lbm_handle *h, size_t bytes) {
     if (h->pinned) (void)hipHostFree(h->pinned);
     h->pinned = nullptr;
     h->pinned_bytes = 0;
-    void *p = nullptr;
-    HIP_TRY(hipHostMalloc(&p, bytes, hipHostMallocDefault));
-    h->pinned = static_cast<double *>(p);
-    h->pinned_bytes = bytes;
+    size_t got = 0;
+    h->pinned = static_cast<double *>(pinned_alloc(bytes, got));
+    h->pinned_bytes = got;
 }
 
 template <typename T>
@@ -607,7 +724,6 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
     ensure_pinned(h, 64 * sizeof(double));
     uprev_from_state<T>(h);
     const int64_t nparts = partial_count(h);
-    double *red = h->red.as<double>();
     int64_t done = 0;
     double r = h->last_residual;
     int status = LBM_OK;
@@ -619,9 +735,8 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
         if (timed) HIP_TRY(hipEventRecord(h->ev[0], h->stream));
         advance<T>(h, chunk, true);
         if (timed) HIP_TRY(hipEventRecord(h->ev[1], h->stream));
-        HIP_TRY(launch_finalize4(h->partials.as<double>(), nparts, red, h->stream));
-        HIP_TRY(hipMemcpyAsync(h->pinned, red, 4 * sizeof(double),
-                               hipMemcpyDeviceToHost, h->stream));
+        // the reduction writes straight into pinned host memory (no copy)
+        HIP_TRY(launch_finalize4(h->partials.as<double>(), nparts, h->pinned, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
         done += chunk;
         h->steps += chunk;
@@ -934,8 +1049,9 @@ double batch_run_impl(lbm_batch *b, int64_t steps) {
         if (b->pinned) (void)hipHostFree(b->pinned);
         b->pinned = nullptr;
         b->pinned_bytes = 0;
-        HIP_TRY(hipHostMalloc(&b->pinned, bytes, hipHostMallocDefault));
-        b->pinned_bytes = bytes;
+        size_t got = 0;
+        b->pinned = pinned_alloc(bytes, got);
+        b->pinned_bytes = got;
     }
     SweepArgs<T> *pa = static_cast<SweepArgs<T> *>(b->pinned);
     for (size_t i = 0; i < n; ++i) {
@@ -1076,7 +1192,9 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
 void lbm_destroy(lbm_handle *h) {
     if (!h) return;
     (void)hipSetDevice(h->device);
-    (void)hipStreamSynchronize(h->stream);
+    // Batches synchronise before returning, so after this no queued work
+    // reads the handle's memory and its blocks can be recycled.
+    if (hipStreamSynchronize(h->stream) == hipSuccess) h->recycle();
     delete h;
 }
 
@@ -1240,8 +1358,8 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
             uint64_t *kf = h->cand.as<uint64_t>();
             uint64_t *hf = kf + cap, *ks = kf + 2 * cap, *hs = kf + 3 * cap;
             int32_t *if_ = reinterpret_cast<int32_t *>(kf + 4 * cap), *is = if_ + cap;
-            HIP_TRY(hipMemsetAsync(counters, 0, 4 * sizeof(unsigned long long), h->stream));
-            HIP_TRY(hipMemsetAsync(err, 0, sizeof(int), h->stream));
+            // counters[0..3] and the error flag (counters + 4) in one fill
+            HIP_TRY(hipMemsetAsync(counters, 0, 5 * sizeof(unsigned long long), h->stream));
             KeysArgs ka;
             ka.types = h->types.as<uint8_t>();
             ka.rho = m;
@@ -1296,10 +1414,8 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
             h->sel.ensure(2 * (size_t)keff * sizeof(int32_t));
             int32_t *srem = h->sel.as<int32_t>(), *sadd = srem + keff;
             h->select_tmp.ensure(select_scratch_bytes(cap));
-            HIP_TRY(launch_select(kf, hf, if_, (int64_t)cnt[0], keff, srem, h->select_tmp.p, cap,
-                                  h->stream));
-            HIP_TRY(launch_select(ks, hs, is, (int64_t)cnt[1], keff, sadd, h->select_tmp.p, cap,
-                                  h->stream));
+            HIP_TRY(launch_select_pair(kf, hf, if_, (int64_t)cnt[0], ks, hs, is, (int64_t)cnt[1],
+                                       keff, srem, sadd, h->select_tmp.p, cap, h->stream));
             h->removed_rho.ensure((size_t)keff * sizeof(double));
             double *rrho = h->removed_rho.as<double>();
             HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, rrho, m,
@@ -1310,14 +1426,18 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
                     zero_cells<decltype(t)>(h, sadd, (int)keff);
                 });
             }
-            HIP_TRY(hipMemcpyAsync(rem.data(), srem, keff * sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(hipMemcpyAsync(add.data(), sadd, keff * sizeof(int32_t),
-                                   hipMemcpyDeviceToHost, h->stream));
-            std::vector<double> rr(keff);
-            HIP_TRY(hipMemcpyAsync(rr.data(), rrho, keff * sizeof(double),
-                                   hipMemcpyDeviceToHost, h->stream));
+            // both index lists (adjacent in sel) and the removed densities
+            // come back through pinned memory in two copies
+            ensure_pinned(h, (size_t)keff * (2 * sizeof(int32_t) + sizeof(double)));
+            double *rr = h->pinned;
+            int32_t *ix = reinterpret_cast<int32_t *>(h->pinned + keff);
+            HIP_TRY(hipMemcpyAsync(rr, rrho, keff * sizeof(double), hipMemcpyDeviceToHost,
+                                   h->stream));
+            HIP_TRY(hipMemcpyAsync(ix, srem, 2 * keff * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   h->stream));
             HIP_TRY(hipStreamSynchronize(h->stream));
+            std::memcpy(rem.data(), ix, keff * sizeof(int32_t));
+            std::memcpy(add.data(), ix + keff, keff * sizeof(int32_t));
             for (int64_t k = 0; k < keff; ++k) mass_removed += rr[k];  // selection order
         }
         if (p->reinit == LBM_COLD) {
@@ -1659,7 +1779,14 @@ int lbm_batch_info(lbm_batch *b, int64_t *items, int32_t *steps_per_launch_out,
 void lbm_batch_destroy(lbm_batch *b) {
     if (!b) return;
     (void)hipSetDevice(b->device);
-    (void)hipStreamSynchronize(b->stream);
+    if (hipStreamSynchronize(b->stream) == hipSuccess) {  // nothing queued reads them now
+        b->args.recycle();
+        b->lat.recycle();
+        b->tiles.recycle();
+        if (b->pinned) host_cache().give(-1, b->pinned_bytes, b->pinned);
+        b->pinned = nullptr;
+        b->pinned_bytes = 0;
+    }
     delete b;
 }
 

@@ -231,13 +231,15 @@ hipError_t launch_digest(const T *f, const uint16_t *cell, const uint8_t *types,
                          int ny, int pitch, size_t plane, unsigned long long *out,
                          hipStream_t s);
 hipError_t launch_keys(const KeysArgs &a, hipStream_t s);
-// The k_eff first of `count` candidates in the order (key, hash), written as
-// cell indices to sel.  `scratch` holds select_scratch_bytes(cap) bytes,
-// count <= cap.
+// The k_eff first of the nf fluid and of the ns solid candidates, each list in
+// the order (key, hash), written as cell indices to sel_f and sel_s.
+// `scratch` holds select_scratch_bytes(cap) bytes; nf, ns <= cap and
+// k_eff <= min(nf, ns).
 size_t select_scratch_bytes(int64_t cap);
-hipError_t launch_select(const uint64_t *key, const uint64_t *hash, const int32_t *idx,
-                         int64_t count, int64_t k_eff, int32_t *sel, void *scratch,
-                         int64_t cap, hipStream_t s);
+hipError_t launch_select_pair(const uint64_t *kf, const uint64_t *hf, const int32_t *if_,
+                              int64_t nf, const uint64_t *ks, const uint64_t *hs,
+                              const int32_t *is, int64_t ns, int64_t k_eff, int32_t *sel_f,
+                              int32_t *sel_s, void *scratch, int64_t cap, hipStream_t s);
 // Flip the selected cells; removed_rho[k] = rho[removed[k]].
 hipError_t launch_flip(uint8_t *types, const int32_t *removed,
                        const int32_t *added, int k_eff, double *removed_rho,

@@ -467,13 +467,11 @@ __global__ __launch_bounds__(256) void keys_kernel(KeysArgs a) {
 #pragma clang fp contract(off)
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
-    if (x < a.band_x || x > a.nx - 1 - a.band_x || y < a.band_y ||
-        y > a.ny - 1 - a.band_y)
-        return;
     const int nx = a.nx;
-    const size_t l = (size_t)y * nx + x;
-    const uint8_t t = a.types[l];
-    if (t != kFluid && t != kSolid) return;
+    const bool in_band = x >= a.band_x && x <= a.nx - 1 - a.band_x && y >= a.band_y &&
+                         y <= a.ny - 1 - a.band_y;
+    const size_t l = in_band ? (size_t)y * nx + x : 0;
+    const uint8_t t = in_band ? a.types[l] : (uint8_t)0xff;
     const int ddx[4] = {1, 0, -1, 0};
     const int ddy[4] = {0, 1, 0, -1};
     bool touch = false;
@@ -483,13 +481,14 @@ __global__ __launch_bounds__(256) void keys_kernel(KeysArgs a) {
 #pragma unroll
         for (int d = 0; d < 4; ++d)
             touch |= a.types[l + ddx[d] + (ptrdiff_t)ddy[d] * nx] == kSolid;
-        if (!touch) return;
-        const double ux = a.ux[l], uy = a.uy[l];
-        const double t1 = ux * ux;
-        const double t2 = uy * uy;
-        const double t3 = t1 + t2;
-        key = a.criterion == kCritPaper ? a.rho[l] * t3 : t3;
-    } else {
+        if (touch) {
+            const double ux = a.ux[l], uy = a.uy[l];
+            const double t1 = ux * ux;
+            const double t2 = uy * uy;
+            const double t3 = t1 + t2;
+            key = a.criterion == kCritPaper ? a.rho[l] * t3 : t3;
+        }
+    } else if (t == kSolid) {
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const size_t m = l + ddx[d] + (ptrdiff_t)ddy[d] * nx;
@@ -506,24 +505,34 @@ __global__ __launch_bounds__(256) void keys_kernel(KeysArgs a) {
                 if (s > key) key = s;
             }
         }
-        if (!touch) return;
     }
-    if (!(key >= 0.0)) bad = true;
-    if (bad) {
-        atomicOr(a.error, 1);
-        return;
+    if (touch && !(key >= 0.0)) bad = true;
+    if (bad) atomicOr(a.error, 1);
+    const bool is_f = touch && !bad && t == kFluid, is_s = touch && !bad && t == kSolid;
+    // One counter update per wave and list (each row of the block is a wave):
+    // lane k of the wave takes slot base + (candidates below lane k).
+    const int lane = threadIdx.x;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint64_t mf = __ballot(is_f), ms = __ballot(is_s);
+    unsigned long long bf = 0, bs = 0;
+    if (lane == 0) {
+        if (mf) bf = atomicAdd(a.count_f, (unsigned long long)__popcll(mf));
+        if (ms) bs = atomicAdd(a.count_s, (unsigned long long)__popcll(ms));
     }
+    bf = __shfl(bf, 0, 64);
+    bs = __shfl(bs, 0, 64);
+    if (!is_f && !is_s) return;
     const uint64_t kb = key_bits(key);
     const uint64_t h = splitmix64(a.seed + (uint64_t)l);
-    if (t == kFluid) {
-        const unsigned long long s = atomicAdd(a.count_f, 1ull);
+    if (is_f) {
+        const unsigned long long s = bf + (unsigned long long)__popcll(mf & below);
         if (s < (unsigned long long)a.cap) {
             a.kf[s] = kb;
             a.hf[s] = h;
             a.if_[s] = (int32_t)l;
         }
     } else {
-        const unsigned long long s = atomicAdd(a.count_s, 1ull);
+        const unsigned long long s = bs + (unsigned long long)__popcll(ms & below);
         if (s < (unsigned long long)a.cap) {
             a.ks[s] = ~kb;
             a.hs[s] = h;
