@@ -228,10 +228,17 @@ int lbm_get_macro(lbm_handle *h, double *rho, double *ux, double *uy,
 int lbm_get_state(lbm_handle *h, double *f, size_t n);
 int lbm_set_state(lbm_handle *h, const double *f, size_t n);
 
-/* Device bytes a handle for d would allocate (0 if d is invalid). */
+/* Device bytes a handle for d would allocate (0 if d is invalid), each
+ * buffer counted in the size class it is allocated in (its size rounded up
+ * to a multiple of 1/8 of its power of two). */
 size_t lbm_footprint_bytes(const lbm_geometry_desc *d);
 
-/* Release a handle and its device memory (NULL is ignored). */
+/* Release a handle (NULL is ignored).  The call waits for the handle's
+ * stream; its device blocks and pinned staging then go to a process-wide
+ * cache that later handles and batches of the same size classes draw from
+ * (at most 4 GiB of device and 64 MiB of pinned host memory are kept, the
+ * oldest blocks being freed first).  A batch that still holds the handle
+ * must be destroyed first. */
 void lbm_destroy(lbm_handle *h);
 
 /* Message of the last error on this thread ("" if none). */
@@ -352,7 +359,9 @@ int lbm_batch_tune(lbm_batch *b, int32_t trial_steps, int32_t *best_variant,
 int lbm_batch_info(lbm_batch *b, int64_t *items, int32_t *steps_per_launch,
                    int64_t *nonsolid_cells);
 
-/* Release a batch (the member handles are untouched; NULL is ignored). */
+/* Release a batch (the member handles are untouched; NULL is ignored).  The
+ * call waits for the batch's stream; its buffers go to the same cache as a
+ * handle's. */
 void lbm_batch_destroy(lbm_batch *b);
 
 /* Switch the captured-graph replay of a batch's time loop on (default) or

@@ -327,7 +327,7 @@ struct lbm_handle {
     int cur = 0;  // buffer holding the current state
     DeviceBuffer cell, types, uin, uprev, partials, red, out_rows, bnd;
     DeviceBuffer macro;  // 3*nx*ny doubles (rho, ux, uy), on demand
-    DeviceBuffer cand, sel, select_tmp, removed_rho;
+    DeviceBuffer cand, sel, select_tmp;
     int64_t cand_cap = 0;
     double *pinned = nullptr;  // small host staging for readbacks
     size_t pinned_bytes = 0;
@@ -385,7 +385,7 @@ struct lbm_handle {
     void recycle() {
         DeviceBuffer *bufs[] = {&f[0], &f[1], &cell, &types, &uin, &uprev, &partials,
                                 &red, &out_rows, &bnd, &macro, &cand, &sel, &select_tmp,
-                                &removed_rho, &tiles};
+                                &tiles};
         for (DeviceBuffer *b : bufs) b->recycle();
         if (pinned) host_cache().give(-1, pinned_bytes, pinned);
         pinned = nullptr;
@@ -1411,31 +1411,25 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
         std::vector<int32_t> rem(keff), add(keff);
         double mass_removed = 0.0;
         if (keff > 0) {
-            h->sel.ensure(2 * (size_t)keff * sizeof(int32_t));
-            int32_t *srem = h->sel.as<int32_t>(), *sadd = srem + keff;
+            // sel: the removed cells' densities, then the removed and the
+            // added cell lists (the layout the pinned readback mirrors)
+            h->sel.ensure((size_t)keff * (sizeof(double) + 2 * sizeof(int32_t)));
+            double *rrho = h->sel.as<double>();
+            int32_t *srem = reinterpret_cast<int32_t *>(rrho + keff), *sadd = srem + keff;
             h->select_tmp.ensure(select_scratch_bytes(cap));
             HIP_TRY(launch_select_pair(kf, hf, if_, (int64_t)cnt[0], ks, hs, is, (int64_t)cnt[1],
                                        keff, srem, sadd, h->select_tmp.p, cap, h->stream));
-            h->removed_rho.ensure((size_t)keff * sizeof(double));
-            double *rrho = h->removed_rho.as<double>();
             HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, rrho, m,
                                 h->stream));
-            if (p->reinit == LBM_WARM) {
-                with_storage(h->precision, [&](auto t) {
-                    zero_cells<decltype(t)>(h, srem, (int)keff);
-                    zero_cells<decltype(t)>(h, sadd, (int)keff);
-                });
-            }
-            // both index lists (adjacent in sel) and the removed densities
-            // come back through pinned memory in two copies
-            ensure_pinned(h, (size_t)keff * (2 * sizeof(int32_t) + sizeof(double)));
-            double *rr = h->pinned;
-            int32_t *ix = reinterpret_cast<int32_t *>(h->pinned + keff);
-            HIP_TRY(hipMemcpyAsync(rr, rrho, keff * sizeof(double), hipMemcpyDeviceToHost,
-                                   h->stream));
-            HIP_TRY(hipMemcpyAsync(ix, srem, 2 * keff * sizeof(int32_t), hipMemcpyDeviceToHost,
-                                   h->stream));
+            if (p->reinit == LBM_WARM)  // removed and added cells, adjacent in sel
+                with_storage(h->precision,
+                             [&](auto t) { zero_cells<decltype(t)>(h, srem, 2 * (int)keff); });
+            ensure_pinned(h, (size_t)keff * (sizeof(double) + 2 * sizeof(int32_t)));
+            HIP_TRY(hipMemcpyAsync(h->pinned, rrho, keff * (sizeof(double) + 2 * sizeof(int32_t)),
+                                   hipMemcpyDeviceToHost, h->stream));
             HIP_TRY(hipStreamSynchronize(h->stream));
+            const double *rr = h->pinned;
+            const int32_t *ix = reinterpret_cast<const int32_t *>(h->pinned + keff);
             std::memcpy(rem.data(), ix, keff * sizeof(int32_t));
             std::memcpy(add.data(), ix + keff, keff * sizeof(int32_t));
             for (int64_t k = 0; k < keff; ++k) mass_removed += rr[k];  // selection order

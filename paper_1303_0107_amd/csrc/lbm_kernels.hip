@@ -542,19 +542,16 @@ __global__ __launch_bounds__(256) void keys_kernel(KeysArgs a) {
 }
 
 // Apply the exchange to the logical type map.
+// Flip the selected cells and record the density of each removed one, in
+// selection order.
 __global__ void flip_kernel(uint8_t *types, const int32_t *removed,
-                            const int32_t *added, int k_eff) {
+                            const int32_t *added, int k_eff, const double *rho,
+                            double *removed_rho) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= k_eff) return;
+    removed_rho[k] = rho[removed[k]];
     types[removed[k]] = kSolid;
     types[added[k]] = kFluid;
-}
-
-// Density of each removed cell, in selection order.
-__global__ void removed_rho_kernel(const double *rho, const int32_t *removed, int k_eff,
-                                   double *out) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < k_eff) out[k] = rho[removed[k]];
 }
 
 // ---------------------------------------------------------------------------
@@ -702,10 +699,8 @@ hipError_t launch_flip(uint8_t *types, const int32_t *removed,
                        const int32_t *added, int k_eff, double *removed_rho,
                        const double *rho, hipStream_t s) {
     if (k_eff <= 0) return hipSuccess;
-    hipLaunchKernelGGL(removed_rho_kernel, dim3((k_eff + 255) / 256), dim3(256), 0, s, rho,
-                       removed, k_eff, removed_rho);
     hipLaunchKernelGGL(flip_kernel, dim3((k_eff + 255) / 256), dim3(256), 0, s,
-                       types, removed, added, k_eff);
+                       types, removed, added, k_eff, rho, removed_rho);
     return hipGetLastError();
 }
 

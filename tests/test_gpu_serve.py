@@ -156,3 +156,31 @@ def test_invalid_requests_are_refused():
     srv.close()
     with pytest.raises(lbm.LbmError):
         lbm.Server(hbm_budget=0)
+
+
+def test_recycled_memory_does_not_leak_into_results():
+    """Destroyed handles hand their blocks to an allocation cache; a new
+    lattice of the same size takes them with the previous lattice's data
+    still in them.  Its result must not depend on that: the same request
+    before and after another lattice of that size has run and been
+    destroyed gives the same digest and statistics, bit for bit."""
+    c = I.batch_candidates(count=3, seed=33)[0]
+
+    def solve(u_peak, prec, shape=True):
+        lat = lbm.Lattice(I.distributor(c.nx, c.ny, c.levels, c.widths), c.tau, u_peak,
+                          precision=prec)
+        lat.run(150, 0.0, 50)
+        if shape:
+            lat.shape_update(frac=0.01, seed=3)
+            lat.run(40, 0.0, 40)
+        flow, st = lat.stats()
+        d = lat.digest()
+        lat.close()
+        # compared as bytes, so that NaN statistics compare equal to themselves
+        return np.asarray(flow).tobytes(), np.array([st.dp, st.theta, st.dg]).tobytes(), d
+
+    for prec in (lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F32_S_F16):
+        first = solve(c.u_peak, prec)
+        solve(2.0 * c.u_peak, prec)  # different data left in the cached blocks
+        again = solve(c.u_peak, prec)
+        assert first == again
