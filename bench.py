@@ -41,24 +41,27 @@ MEASURED_TRAFFIC_PER_STEP = {
     # shape 1 (32x64 dense regions, 8 steps per launch), 234 active tiles
     ("distributor-1024x512-L3", "f32", 1): 14.922e6 / 8,
     # shape 0 (32x64 compacted regions)
-    ("distributor-1024x512-L3", "f32", 0): 14.980e6 / 8,
+    ("distributor-1024x512-L3", "f32", 0): 14.977e6 / 8,
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
 MEASURED_TRAFFIC_PER_LAUNCH = {
-    # profiles/sweep_batch_float_batch-256-candidates.txt; shapes 0..3 temporal
+    # profiles/sweep_batch_float_batch-256-candidates.txt; shapes 0..4 temporal
     # blocking (0: 32x64 compacted, 1: 32x64 dense, 2: 32x64 compacted with
-    # 4 steps per launch, 3: 16x64 compacted), 4 = one step per launch
-    ("batch-256-candidates", "f32", 3, 1): 700.897e6,
-    ("batch-256-candidates", "f32", 3, 0): 1366.046e6,
-    ("batch-256-candidates", "f32", 2, 1): 708.340e6,
-    ("batch-256-candidates", "f32", 2, 0): 1090.874e6,
-    ("batch-256-candidates", "f32", 1, 1): 709.149e6,
-    ("batch-256-candidates", "f32", 1, 0): 1556.313e6,
-    ("batch-256-candidates", "f32", 0, 1): 709.206e6,
-    ("batch-256-candidates", "f32", 0, 0): 1556.429e6,
-    ("batch-256-candidates", "f32", 4, 1): 684.535e6,
-    ("batch-256-candidates", "f32", 4, 0): 775.491e6,
+    # 4 steps per launch, 3: 16x64 compacted, 4: 16x64 dense), 5 = one step
+    # per launch
+    ("batch-256-candidates", "f32", 4, 1): 700.885e6,
+    ("batch-256-candidates", "f32", 4, 0): 1366.032e6,
+    ("batch-256-candidates", "f32", 3, 1): 700.900e6,
+    ("batch-256-candidates", "f32", 3, 0): 1366.047e6,
+    ("batch-256-candidates", "f32", 2, 1): 708.365e6,
+    ("batch-256-candidates", "f32", 2, 0): 1090.869e6,
+    ("batch-256-candidates", "f32", 1, 1): 709.154e6,
+    ("batch-256-candidates", "f32", 1, 0): 1556.319e6,
+    ("batch-256-candidates", "f32", 0, 1): 709.211e6,
+    ("batch-256-candidates", "f32", 0, 0): 1556.427e6,
+    ("batch-256-candidates", "f32", 5, 1): 684.535e6,
+    ("batch-256-candidates", "f32", 5, 0): 775.492e6,
 }
 
 

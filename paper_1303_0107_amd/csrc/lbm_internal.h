@@ -158,19 +158,14 @@ struct TbVariants<double> {
 };
 template <>
 struct TbVariants<float> {
-    static constexpr int count = 4;
-    static constexpr TbVariant v[4] = {{32, 8, true}, {32, 8, false}, {32, 4, true}, {16, 4, true}};
+    static constexpr int count = 5;
+    static constexpr TbVariant v[5] = {
+        {32, 8, true}, {32, 8, false}, {32, 4, true}, {16, 4, true}, {16, 4, false}};
 };
 template <>
-struct TbVariants<h16> {
-    static constexpr int count = 4;
-    static constexpr TbVariant v[4] = {{32, 8, true}, {32, 8, false}, {32, 4, true}, {16, 4, true}};
-};
+struct TbVariants<h16> : TbVariants<float> {};
 template <>
-struct TbVariants<bf16> {
-    static constexpr int count = 4;
-    static constexpr TbVariant v[4] = {{32, 8, true}, {32, 8, false}, {32, 4, true}, {16, 4, true}};
-};
+struct TbVariants<bf16> : TbVariants<float> {};
 constexpr int kTbThreads = 1024;
 template <typename T>
 constexpr int tile_w(int variant) { return 64 - 2 * TbVariants<T>::v[variant].halo; }
