@@ -78,7 +78,7 @@ typedef struct lbm_handle lbm_handle;
 
 /* Geometry and physics of one lattice. */
 typedef struct {
-    int32_t nx, ny;     /* lattice size: 3 <= nx, 3 <= ny, nx*ny < 2^31   */
+    int32_t nx, ny;     /* lattice size: 3 <= nx, ny <= 65536, nx*ny < 2^31 */
     int32_t levels;     /* generator only: bifurcation generations L >= 1 */
     int32_t widths[9];  /* generator only: w_0..w_L in cells; all 0 gives
                            w_k = max(2, (ny/8) >> k)                      */

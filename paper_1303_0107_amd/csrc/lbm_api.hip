@@ -267,8 +267,9 @@ bool check_desc(const lbm_geometry_desc *d, std::string &why) {
         why = "nx and ny must be >= 3";
         return false;
     }
-    if ((int64_t)d->nx * d->ny >= (int64_t)1 << 31) {
-        why = "nx*ny must be < 2^31";
+    // work lists pack a tile or block column and row into 16 + 15 bits
+    if (d->nx > 65536 || d->ny > 65536 || (int64_t)d->nx * d->ny >= (int64_t)1 << 31) {
+        why = "nx and ny must be <= 65536 and nx*ny < 2^31";
         return false;
     }
     if (!(d->tau > 0.5) || !std::isfinite(d->tau)) {

@@ -57,6 +57,10 @@ def test_footprint_and_validation_need_no_device(lib):
     assert lbm.lbm_footprint_bytes(bad) == 0
     bad = lbm.make_desc(2, 512, 0.6, 0.04)
     assert lbm.lbm_footprint_bytes(bad) == 0
+    # work lists pack tile columns and rows into 16 and 15 bits: sides <= 65536
+    assert lbm.lbm_footprint_bytes(lbm.make_desc(65536, 16, 0.6, 0.04)) > 0
+    assert lbm.lbm_footprint_bytes(lbm.make_desc(65537, 16, 0.6, 0.04)) == 0
+    assert lbm.lbm_footprint_bytes(lbm.make_desc(16, 65537, 0.6, 0.04)) == 0
 
 
 def test_invalid_descriptor_is_rejected_before_any_device_call(lib):
