@@ -277,6 +277,15 @@ int32_t lbm_tb_variant_count(int32_t precision);
 int lbm_tb_variant_info(int32_t precision, int32_t variant, int32_t *rows,
                         int32_t *halo, int32_t *tile_w, int32_t *tile_h);
 
+/* Body of shape `variant` of `precision`: kind LBM_TB_DENSE (a lane per
+ * region column, two region copies), LBM_TB_COMPACT (lanes take entries of a
+ * list of the region's non-solid cells; two copies plus the list) or
+ * LBM_TB_INPLACE (dense, one copy updated in place), and the LDS bytes one
+ * workgroup of it uses.  Any output pointer may be NULL.  Errors: LBM_EINVAL. */
+enum { LBM_TB_DENSE = 0, LBM_TB_COMPACT = 1, LBM_TB_INPLACE = 2 };
+int lbm_tb_variant_kind(int32_t precision, int32_t variant, int32_t *kind,
+                        int32_t *lds_bytes);
+
 /* Use region shape `variant` for the handle's sweeps from now on.
  * Errors: LBM_EINVAL (NULL handle, variant out of range), LBM_EHIP. */
 int lbm_set_tb_variant(lbm_handle *h, int32_t variant);

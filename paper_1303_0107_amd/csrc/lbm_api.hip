@@ -1575,6 +1575,21 @@ int lbm_tb_variant_info(int32_t precision, int32_t variant, int32_t *rows, int32
     return LBM_OK;
 }
 
+int lbm_tb_variant_kind(int32_t precision, int32_t variant, int32_t *kind,
+                        int32_t *lds_bytes) {
+    g_error.clear();
+    if (variant < 0 || variant >= lbm_tb_variant_count(precision))
+        return fail(LBM_EINVAL, "unknown precision or shape");
+    const TbVariant v = tb_shape(precision, variant);
+    if (kind) *kind = v.kind;
+    // the region copies (one when updated in place), plus the compacted list
+    if (lds_bytes)
+        *lds_bytes = (int32_t)((v.kind == kTbInPlace ? 1 : 2) * 9 * 64 * (size_t)v.rows *
+                                   elem_size(precision) +
+                               (v.kind == kTbCompact ? 64 * (size_t)v.rows * 4 : 0));
+    return LBM_OK;
+}
+
 int lbm_set_tb_variant(lbm_handle *h, int32_t variant) {
     g_error.clear();
     if (!h) return fail(LBM_EINVAL, "null handle");

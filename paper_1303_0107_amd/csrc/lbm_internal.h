@@ -140,27 +140,34 @@ hipError_t launch_sweep(const SweepArgs<T> &a, bool check, hipStream_t s);
 // Temporal blocking: regions of 64 x rows cells with a halo of `halo` cells
 // (so up to `halo` steps per launch), tiles of (64 - 2 halo) x (rows - 2 halo)
 // cells, 1024 threads per workgroup, two LDS copies of the region
-// (9 * 64 * rows * sizeof(T) bytes each) and, in the compacted form, a list
-// of the region's non-solid cells (4 bytes per region cell); at most 160 KB
-// in all.  A few shapes are compiled per storage type; variant 0 is the
+// (9 * 64 * rows * sizeof(T) bytes each; one copy in the in-place form) and,
+// in the compacted form, a list of the region's non-solid cells (4 bytes per
+// region cell); at most 160 KB in all.  A few shapes are compiled per storage type; variant 0 is the
 // default, the autotuner may pick another.  The shape never changes the
 // results, only the speed.
+// Region bodies: dense (a lane per region column), compacted (lanes take
+// consecutive entries of a list of the region's non-solid cells), or dense
+// with one region copy updated in place (half the LDS, so taller regions).
+enum TbKind : int { kTbDense = 0, kTbCompact = 1, kTbInPlace = 2 };
 struct TbVariant {
-    int rows, halo;
-    bool compact;
+    int rows, halo, kind;
 };
 template <typename T>
 struct TbVariants;
 template <>
 struct TbVariants<double> {
-    static constexpr int count = 3;
-    static constexpr TbVariant v[3] = {{16, 4, true}, {16, 4, false}, {16, 2, true}};
+    static constexpr int count = 4;
+    static constexpr TbVariant v[4] = {
+        {16, 4, kTbCompact}, {16, 4, kTbDense}, {16, 2, kTbCompact}, {32, 8, kTbInPlace}};
 };
 template <>
 struct TbVariants<float> {
     static constexpr int count = 5;
-    static constexpr TbVariant v[5] = {
-        {32, 8, true}, {32, 8, false}, {32, 4, true}, {16, 4, true}, {16, 4, false}};
+    static constexpr TbVariant v[5] = {{32, 8, kTbCompact},
+                                       {32, 8, kTbDense},
+                                       {32, 4, kTbCompact},
+                                       {16, 4, kTbCompact},
+                                       {16, 4, kTbDense}};
 };
 template <>
 struct TbVariants<h16> : TbVariants<float> {};

@@ -302,6 +302,130 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
     }
 }
 
+// Temporal blocking with one region copy, updated in place: at each step
+// every thread first pulls the nine populations of each of its cells into
+// registers, and after a barrier relaxes them and writes them back (two
+// barriers per step).  Half the LDS of the two-copy form, so regions twice
+// as tall fit (FP64 64 x 32: 147 KB).  Cells, depths and the order of the
+// arithmetic are those of the two-copy form, so the results are the same
+// bits.
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC>
+__device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T> &a,
+                                                const int t, const int steps,
+                                                double *part_out) {
+    using T = typename Cell::T;
+    using CT = typename Cell::CT;
+    constexpr int RW = 64, IW = RW - 2 * H, IH = RH - 2 * H;
+    constexpr int NW = NT / 64, CPT = RH / NW, PL = RW * RH;
+    static_assert(RH % NW == 0, "region rows must split evenly over waves");
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *L = reinterpret_cast<T *>(lds_raw);
+
+    const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int gx = ox + lane;
+    const bool col_in = gx >= 0 && gx < a.nx;
+
+    uint32_t cw[CPT];
+    int depth[CPT];
+    UinT<T> uin[CPT];  // inlet velocity of the thread's cells, read once per launch
+    T v[CPT][9];
+    size_t n[CPT];
+    // cell words, then populations, then the LDS stores (as in the two-copy form)
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int gy = oy + wave + c * NW;
+        const bool in = col_in && gy >= 0 && gy < a.ny;
+        n[c] = in ? (size_t)gy * a.pitch + gx : 0;
+        cw[c] = in ? a.cell[n[c]] : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int ry = wave + c * NW, gy = oy + ry;
+        const bool live = cell_type(cw[c]) != kSolid;  // cells off the lattice read as solid
+        depth[c] = live ? min(min(lane, RW - 1 - lane), min(ry, RH - 1 - ry)) : 0;
+        uin[c] = cell_type(cw[c]) == kInlet ? a.uin[gy] : UinT<T>(0);
+        if (live) {
+            const T *p = a.fin + n[c];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[c][i] = p[(size_t)i * a.plane];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[c][i] = Cell::store(CT(0));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) L[i * PL + (wave + c * NW) * RW + lane] = v[c][i];
+    __syncthreads();
+
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    // Pulls of one cell (its nine populations after streaming, and for a
+    // Neumann outlet the neighbour's velocity).
+    auto pull = [&](const int c, CT (&f)[9], CT &bx, CT &by) {
+        const int ry = wave + c * NW, gy = oy + ry, pos = ry * RW + lane;
+        const uint32_t type = update_type(cw[c]);
+        bx = type == kInlet ? (CT)uin[c] : CT(0);
+        by = CT(0);
+        if (BC && type == kOutletNeumann && (cw[c] & kWordLeftLive)) {
+            CT g[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) g[i] = Cell::load(L[i * PL + pos - 1]);
+            Cell::velocity(g, bx, by);
+        }
+        if (BC && (cw[c] & kWordGeneral)) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                f[i] = Cell::load(L[general_src(cw[c], i, lane, ry, gy, a.ny, a.flags, PL, RW)]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const bool wall = i > 0 && ((cw[c] >> (i - 1)) & 1u);
+                f[i] = Cell::load(L[wall ? kOpp[i] * PL + pos : i * PL + pos - kCy[i] * RW - kCx[i]]);
+            }
+        }
+    };
+    for (int s = 1; s < steps; ++s) {
+        // every read of the step, then a barrier, then the in-place writes
+        CT f[CPT][9], bx[CPT], by[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+            if (depth[c] >= s) pull(c, f[c], bx[c], by[c]);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            if (depth[c] < s) continue;
+            double mass, ux, uy;
+            Cell::update(f[c], update_type(cw[c]), bx[c], by[c], a, mass, ux, uy);
+            const int pos = (wave + c * NW) * RW + lane;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) L[i * PL + pos] = Cell::store(f[c][i]);
+        }
+        __syncthreads();
+    }
+    // The last step writes to HBM only, so each cell is pulled and updated in turn.
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        if (depth[c] < H) continue;  // the tile cells
+        CT f[9], bx, by;
+        pull(c, f, bx, by);
+        double mass, ux, uy;
+        Cell::update(f, update_type(cw[c]), bx, by, a, mass, ux, uy);
+        const size_t m = (size_t)(oy + wave + c * NW) * a.pitch + gx;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) a.fout[(size_t)i * a.plane + m] = Cell::store(f[i]);
+        if (CHECK) check_terms(a, m, mass, ux, uy, part);
+    }
+    if (CHECK) {
+        block_sum<4, NT>(part);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) part_out[k] = part[k];
+        }
+    }
+}
+
 // Temporal blocking with a compacted cell list.  On sparse geometries most
 // lanes of a region row hold solid cells, so the dense form above issues
 // every wave instruction for a few useful lanes.  Here, after the region is
@@ -488,42 +612,44 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
     }
 }
 
-// One region shape: rows x 64 cells, halo H, dense or compacted.
-template <class Cell, int RH, int H, int NT, bool COMPACT, bool CHECK, bool BC>
+// One region shape: rows x 64 cells, halo H, body KIND (TbKind).
+template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC>
 __device__ __forceinline__ void tb_dispatch(const SweepArgs<typename Cell::T> &a, const int t,
                                             const int steps, double *part_out) {
-    if constexpr (COMPACT)
+    if constexpr (KIND == kTbCompact)
         tb_body_compact<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
+    else if constexpr (KIND == kTbInPlace)
+        tb_body_inplace<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
     else
         tb_body<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
 }
 
-template <class Cell, int RH, int H, int NT, bool COMPACT, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC>
 __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
                                                 const int32_t *__restrict__ tiles,
                                                 int steps) {
-    tb_dispatch<Cell, RH, H, NT, COMPACT, CHECK, BC>(
+    tb_dispatch<Cell, RH, H, NT, KIND, CHECK, BC>(
         a, tiles[blockIdx.x], steps, CHECK ? a.partials + (size_t)blockIdx.x * 4 : nullptr);
 }
 
 // Many lattices in one launch: work item b is tile tiles[b] of lattice
 // lat[b], whose arguments are args[lat[b]]; lat[b] < 0 marks a padding item
 // (the whole workgroup leaves at once, before any barrier).
-template <class Cell, int RH, int H, int NT, bool COMPACT, bool BC>
+template <class Cell, int RH, int H, int NT, int KIND, bool BC>
 __global__ __launch_bounds__(NT) void tb_batch_kernel(
     const SweepArgs<typename Cell::T> *__restrict__ args, const int32_t *__restrict__ lat,
     const int32_t *__restrict__ tiles, int steps) {
     const int l = lat[blockIdx.x];
     if (l < 0) return;
     const SweepArgs<typename Cell::T> a = args[l];
-    tb_dispatch<Cell, RH, H, NT, COMPACT, false, BC>(a, tiles[blockIdx.x], steps, nullptr);
+    tb_dispatch<Cell, RH, H, NT, KIND, false, BC>(a, tiles[blockIdx.x], steps, nullptr);
 }
 
 // Dynamic LDS of one region shape.
-template <typename T, int RH, bool COMPACT>
+template <typename T, int RH, int KIND>
 constexpr size_t tb_lds_bytes() {
-    return (size_t)2 * 9 * 64 * RH * sizeof(T) +
-           (COMPACT ? (size_t)64 * RH * sizeof(uint32_t) : 0);
+    return (size_t)(KIND == kTbInPlace ? 1 : 2) * 9 * 64 * RH * sizeof(T) +
+           (KIND == kTbCompact ? (size_t)64 * RH * sizeof(uint32_t) : 0);
 }
 
 // Host-side launch helpers shared by the per-precision units.
@@ -550,11 +676,11 @@ inline hipError_t set_lds(const void *k, size_t lds, bool &done) {
     return e;
 }
 
-template <class Cell, int RH, int H, int NT, bool COMPACT, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC>
 hipError_t launch_tb_one(const SweepArgs<typename Cell::T> &a, const int32_t *tiles, int n_tiles,
                          int steps, hipStream_t s) {
-    const size_t lds = tb_lds_bytes<typename Cell::T, RH, COMPACT>();
-    auto k = tb_kernel<Cell, RH, H, NT, COMPACT, CHECK, BC>;
+    const size_t lds = tb_lds_bytes<typename Cell::T, RH, KIND>();
+    auto k = tb_kernel<Cell, RH, H, NT, KIND, CHECK, BC>;
     static bool configured = false;  // one flag per kernel instantiation
     const hipError_t e = set_lds((const void *)k, lds, configured);
     if (e != hipSuccess) return e;
@@ -562,26 +688,26 @@ hipError_t launch_tb_one(const SweepArgs<typename Cell::T> &a, const int32_t *ti
     return hipGetLastError();
 }
 
-template <class Cell, int RH, int H, int NT, bool COMPACT>
+template <class Cell, int RH, int H, int NT, int KIND>
 hipError_t launch_tb(const SweepArgs<typename Cell::T> &a, const int32_t *tiles, int n_tiles,
                      int steps, bool check, hipStream_t s) {
     if (n_tiles <= 0 || steps <= 0) return hipSuccess;
     if (steps > H) return hipErrorInvalidValue;
     const bool bc = a.flags != 0;
     if (check && bc)
-        return launch_tb_one<Cell, RH, H, NT, COMPACT, true, true>(a, tiles, n_tiles, steps, s);
+        return launch_tb_one<Cell, RH, H, NT, KIND, true, true>(a, tiles, n_tiles, steps, s);
     if (check)
-        return launch_tb_one<Cell, RH, H, NT, COMPACT, true, false>(a, tiles, n_tiles, steps, s);
+        return launch_tb_one<Cell, RH, H, NT, KIND, true, false>(a, tiles, n_tiles, steps, s);
     if (bc)
-        return launch_tb_one<Cell, RH, H, NT, COMPACT, false, true>(a, tiles, n_tiles, steps, s);
-    return launch_tb_one<Cell, RH, H, NT, COMPACT, false, false>(a, tiles, n_tiles, steps, s);
+        return launch_tb_one<Cell, RH, H, NT, KIND, false, true>(a, tiles, n_tiles, steps, s);
+    return launch_tb_one<Cell, RH, H, NT, KIND, false, false>(a, tiles, n_tiles, steps, s);
 }
 
-template <class Cell, int RH, int H, int NT, bool COMPACT, bool BC>
+template <class Cell, int RH, int H, int NT, int KIND, bool BC>
 hipError_t launch_tb_batch_one(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
                                const int32_t *tiles, int n_items, int steps, hipStream_t s) {
-    const size_t lds = tb_lds_bytes<typename Cell::T, RH, COMPACT>();
-    auto k = tb_batch_kernel<Cell, RH, H, NT, COMPACT, BC>;
+    const size_t lds = tb_lds_bytes<typename Cell::T, RH, KIND>();
+    auto k = tb_batch_kernel<Cell, RH, H, NT, KIND, BC>;
     static bool configured = false;  // one flag per kernel instantiation; set also on an
                                      // empty call, so that it can precede a graph capture
     const hipError_t e = set_lds((const void *)k, lds, configured);
@@ -591,14 +717,14 @@ hipError_t launch_tb_batch_one(const SweepArgs<typename Cell::T> *args, const in
     return hipGetLastError();
 }
 
-template <class Cell, int RH, int H, int NT, bool COMPACT>
+template <class Cell, int RH, int H, int NT, int KIND>
 hipError_t launch_tb_batch(const SweepArgs<typename Cell::T> *args, const int32_t *lat,
                            const int32_t *tiles, int n_items, int steps, bool bc, hipStream_t s) {
     if (steps > H) return hipErrorInvalidValue;
     if (bc)
-        return launch_tb_batch_one<Cell, RH, H, NT, COMPACT, true>(args, lat, tiles, n_items,
+        return launch_tb_batch_one<Cell, RH, H, NT, KIND, true>(args, lat, tiles, n_items,
                                                                        steps, s);
-    return launch_tb_batch_one<Cell, RH, H, NT, COMPACT, false>(args, lat, tiles, n_items,
+    return launch_tb_batch_one<Cell, RH, H, NT, KIND, false>(args, lat, tiles, n_items,
                                                                     steps, s);
 }
 
@@ -623,7 +749,7 @@ hipError_t launch_tb_variant(const SweepArgs<typename Cell::T> &a, const int32_t
     if constexpr (V < TbVariants<T>::count) {
         if (variant == V)
             return launch_tb<Cell, TbVariants<T>::v[V].rows, TbVariants<T>::v[V].halo,
-                             kTbThreads, TbVariants<T>::v[V].compact>(a, tiles, n_tiles,
+                             kTbThreads, TbVariants<T>::v[V].kind>(a, tiles, n_tiles,
                                                                             steps, check, s);
         return launch_tb_variant<Cell, V + 1>(a, tiles, n_tiles, steps, check, variant, s);
     } else {
@@ -639,7 +765,7 @@ hipError_t launch_tb_batch_variant(const SweepArgs<typename Cell::T> *args, cons
     if constexpr (V < TbVariants<T>::count) {
         if (variant == V)
             return launch_tb_batch<Cell, TbVariants<T>::v[V].rows, TbVariants<T>::v[V].halo,
-                                   kTbThreads, TbVariants<T>::v[V].compact>(
+                                   kTbThreads, TbVariants<T>::v[V].kind>(
                 args, lat, tiles, n_items, steps, bc, s);
         return launch_tb_batch_variant<Cell, V + 1>(args, lat, tiles, n_items, steps, variant,
                                                     bc, s);

@@ -27,6 +27,7 @@ LBM_WARM, LBM_COLD = 0, 1
 LBM_CRIT_PAPER, LBM_CRIT_SPEED = 0, 1
 LBM_REQ_SOLVE, LBM_REQ_OPTIMIZE = 0, 1
 LBM_NEUMANN_OUTLET, LBM_SYMMETRY_TOP = 1, 2
+LBM_TB_DENSE, LBM_TB_COMPACT, LBM_TB_INPLACE = 0, 1, 2
 
 
 class LbmError(RuntimeError):
@@ -131,6 +132,7 @@ def load() -> ctypes.CDLL:
         "lbm_profile_sweeps": (ctypes.c_int, [H, i32, P, P, P]),
         "lbm_tb_variant_count": (i32, [i32]),
         "lbm_tb_variant_info": (ctypes.c_int, [i32, i32, P, P, P, P]),
+        "lbm_tb_variant_kind": (ctypes.c_int, [i32, i32, P, P]),
         "lbm_set_tb_variant": (ctypes.c_int, [H, i32]),
         "lbm_autotune": (ctypes.c_int, [H, i32, P, P, i32]),
         "lbm_batch_create": (ctypes.c_int, [P, i32, P, ctypes.POINTER(H)]),
@@ -310,6 +312,15 @@ def lbm_tb_variant_info(precision: int, variant: int):
     """(rows, halo, tile_w, tile_h) of a compiled region shape."""
     v = [ctypes.c_int32(0) for _ in range(4)]
     _check(load().lbm_tb_variant_info(int(precision), int(variant),
+                                      *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+def lbm_tb_variant_kind(precision: int, variant: int):
+    """(kind, LDS bytes per workgroup) of a compiled region shape; kind is
+    LBM_TB_DENSE, LBM_TB_COMPACT or LBM_TB_INPLACE."""
+    v = [ctypes.c_int32(0) for _ in range(2)]
+    _check(load().lbm_tb_variant_kind(int(precision), int(variant),
                                       *[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)
 

@@ -11,7 +11,7 @@ EXPECTED = {
     "lbm_create_geometry", "lbm_run_to_steady", "lbm_outlet_stats", "lbm_shape_update",
     "lbm_last_exchange", "lbm_get_mask", "lbm_get_macro", "lbm_get_state", "lbm_set_state",
     "lbm_footprint_bytes", "lbm_destroy", "lbm_last_error", "lbm_bench_sweep",
-    "lbm_profile_sweeps", "lbm_tb_variant_count", "lbm_tb_variant_info",
+    "lbm_profile_sweeps", "lbm_tb_variant_count", "lbm_tb_variant_info", "lbm_tb_variant_kind",
     "lbm_set_tb_variant", "lbm_autotune", "lbm_batch_create", "lbm_batch_run",
     "lbm_batch_configure", "lbm_batch_tune", "lbm_batch_info", "lbm_batch_destroy",
     "lbm_batch_set_graphs", "lbm_state_digest", "lbm_server_create", "lbm_server_submit",
@@ -73,7 +73,8 @@ def test_invalid_descriptor_is_rejected_before_any_device_call(lib):
 
 def test_region_shapes_fit_the_chip(lib):
     """Host-only queries: every compiled shape leaves an interior tile, its
-    two LDS copies fit 160 KB, and rows split evenly over 16 waves."""
+    region copies (two, or one updated in place) and cell list fit 160 KB,
+    and rows split evenly over 16 waves."""
     sizes = {lbm.LBM_F64: 8, lbm.LBM_F32: 4, lbm.LBM_F32_S_F16: 2, lbm.LBM_F32_S_BF16: 2}
     for prec, es in sizes.items():
         n = lbm.lbm_tb_variant_count(prec)
@@ -81,7 +82,11 @@ def test_region_shapes_fit_the_chip(lib):
         for v in range(n):
             rows, halo, tw, th = lbm.lbm_tb_variant_info(prec, v)
             assert tw == 64 - 2 * halo and th == rows - 2 * halo and th > 0
-            assert 2 * 9 * 64 * rows * es + 64 * rows * 4 <= 160 * 1024  # + cell list
+            kind, lds = lbm.lbm_tb_variant_kind(prec, v)
+            copies = 1 if kind == lbm.LBM_TB_INPLACE else 2
+            listed = 64 * rows * 4 if kind == lbm.LBM_TB_COMPACT else 0
+            assert kind in (lbm.LBM_TB_DENSE, lbm.LBM_TB_COMPACT, lbm.LBM_TB_INPLACE)
+            assert lds == copies * 9 * 64 * rows * es + listed <= 160 * 1024
             assert rows % 16 == 0
         with pytest.raises(lbm.LbmError):
             lbm.lbm_tb_variant_info(prec, n)
