@@ -327,6 +327,9 @@ struct lbm_handle {
     DeviceBuffer f[2];
     int cur = 0;  // buffer holding the current state
     DeviceBuffer cell, types, uin, uprev, partials, red, out_rows, bnd;
+    DeviceBuffer ctl;                    // RunControl of lbm_run_to_steady
+    const int *active_stop = nullptr;    // its stop flag while a run is queued
+    hipEvent_t run_ev[2 * kRunBatchMax] = {};  // per-interval timing of a run
     DeviceBuffer macro;  // 3*nx*ny doubles (rho, ux, uy), on demand
     DeviceBuffer cand, sel, select_tmp;
     int64_t cand_cap = 0;
@@ -386,7 +389,7 @@ struct lbm_handle {
     void recycle() {
         DeviceBuffer *bufs[] = {&f[0], &f[1], &cell, &types, &uin, &uprev, &partials,
                                 &red, &out_rows, &bnd, &macro, &cand, &sel, &select_tmp,
-                                &tiles};
+                                &tiles, &ctl};
         for (DeviceBuffer *b : bufs) b->recycle();
         if (pinned) host_cache().give(-1, pinned_bytes, pinned);
         pinned = nullptr;
@@ -406,6 +409,8 @@ struct lbm_handle {
         }
         if (tile_pinned) (void)hipHostFree(tile_pinned);
         for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : run_ev)
             if (e) (void)hipEventDestroy(e);
     }
 };
@@ -592,6 +597,7 @@ SweepArgs<T> sweep_args(lbm_handle *h, bool check) {
     a.uin = h->uin.as<UinT<T>>();
     a.uprev = check ? h->uprev.as<double>() : nullptr;
     a.partials = check ? h->partials.as<double>() : nullptr;
+    a.stop = h->use_tb ? h->active_stop : nullptr;
     a.nx = h->nx;
     a.ny = h->ny;
     a.pitch = h->pitch;
@@ -722,34 +728,77 @@ void macro_dispatch(lbm_handle *h) {
 template <typename T>
 int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
              int64_t *steps_done, double *residual) {
-    ensure_pinned(h, 64 * sizeof(double));
+    ensure_pinned(h, sizeof(RunControl));
     uprev_from_state<T>(h);
     const int64_t nparts = partial_count(h);
+    // Check intervals are queued several at a time (temporal blocking only):
+    // each interval's finalize step decides on the device whether the run
+    // goes on, the launches queued after the deciding one change nothing, and
+    // the host waits once per batch instead of once per interval.  The batch
+    // grows while the residual is far from the tolerance and shrinks near it.
+    h->ctl.ensure(sizeof(RunControl));
+    RunControl *ctl = h->ctl.as<RunControl>();
+    HIP_TRY(hipMemsetAsync(ctl, 0, sizeof(RunControl), h->stream));
+    struct ActiveStop {  // the stop flag reaches the launches of this run only
+        lbm_handle *h;
+        ~ActiveStop() { h->active_stop = nullptr; }
+    } guard{h};
+    h->active_stop = h->use_tb ? &ctl->stop : nullptr;
+    if (h->profiling)
+        for (hipEvent_t &e : h->run_ev)
+            if (!e) HIP_TRY(hipEventCreate(&e));
     int64_t done = 0;
-    double r = h->last_residual;
+    double r = h->last_residual, r_prev = std::nan("");
     int status = LBM_OK;
     bool converged = false;
+    int batch = 1;
     while (done < max_steps) {
-        const int64_t chunk = std::min<int64_t>(k, max_steps - done);
-        const bool timed = h->profiling;
-        const int64_t k0 = h->prof_kernels;
-        if (timed) HIP_TRY(hipEventRecord(h->ev[0], h->stream));
-        advance<T>(h, chunk, true);
-        if (timed) HIP_TRY(hipEventRecord(h->ev[1], h->stream));
-        // the reduction writes straight into pinned host memory (no copy)
-        HIP_TRY(launch_finalize4(h->partials.as<double>(), nparts, h->pinned, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
-        done += chunk;
-        h->steps += chunk;
-        if (timed) {
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
-            h->prof_ms += ms;
-            h->prof_launches += chunk;
-        } else {
+        const int nb = h->use_tb ? batch : 1;
+        int64_t chunk[kRunBatchMax];
+        int cur_after[kRunBatchMax];
+        int64_t kernels[kRunBatchMax];
+        int planned = 0;
+        for (int64_t at = done; planned < nb && at < max_steps; ++planned) {
+            chunk[planned] = std::min<int64_t>(k, max_steps - at);
+            at += chunk[planned];
+            const int64_t k0 = h->prof_kernels;
+            if (h->profiling) HIP_TRY(hipEventRecord(h->run_ev[2 * planned], h->stream));
+            advance<T>(h, chunk[planned], true);
+            if (h->profiling) HIP_TRY(hipEventRecord(h->run_ev[2 * planned + 1], h->stream));
+            kernels[planned] = h->prof_kernels - k0;
             h->prof_kernels = k0;
+            HIP_TRY(launch_finalize_check(h->partials.as<double>(), nparts, ctl, planned, tol,
+                                          h->stream));
+            cur_after[planned] = h->cur;
         }
-        const double num = h->pinned[0], den = h->pinned[1], bad = h->pinned[3];
+        const RunControl *rc = reinterpret_cast<const RunControl *>(h->pinned);
+        HIP_TRY(hipMemcpyAsync(h->pinned, ctl, sizeof(RunControl), hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const int ran = rc->done;
+        if (ran < 1 || ran > planned) throw HipFail{hipErrorUnknown, "run control"};
+        // every interval before the last one carried out must have gone on
+        for (int j = 0; j + 1 < ran; ++j) {
+            const double nj = rc->sums[j][0], dj = rc->sums[j][1];
+            const double rj = dj == 0.0 ? (nj == 0.0 ? 0.0 : INFINITY) : std::sqrt(nj) / std::sqrt(dj);
+            if (rc->sums[j][3] != 0.0 || !std::isfinite(nj) || !std::isfinite(dj) ||
+                (tol > 0.0 && rj < tol))
+                throw HipFail{hipErrorUnknown, "run control disagrees with the residual"};
+        }
+        for (int j = 0; j < ran; ++j) {
+            done += chunk[j];
+            h->steps += chunk[j];
+            if (h->profiling) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, h->run_ev[2 * j], h->run_ev[2 * j + 1]));
+                h->prof_ms += ms;
+                h->prof_launches += chunk[j];
+                h->prof_kernels += kernels[j];
+            }
+        }
+        h->cur = cur_after[ran - 1];  // launches queued after the last interval did nothing
+        const double num = rc->sums[ran - 1][0], den = rc->sums[ran - 1][1],
+                     bad = rc->sums[ran - 1][3];
         if (bad != 0.0 || !std::isfinite(num) || !std::isfinite(den)) {
             r = std::nan("");
             status = fail(LBM_EUNSTABLE, "non-finite density or velocity");
@@ -760,6 +809,20 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
             converged = true;
             break;
         }
+        if (rc->stop != 0 || ran != planned)  // the device stopped where the host would not
+            throw HipFail{hipErrorUnknown, "run control disagrees with the residual"};
+        // next batch: about half the intervals the residual's decay rate
+        // predicts before the tolerance (one when it does not decay)
+        int next = 1;
+        if (tol > 0.0 && r_prev > 0.0 && r > 0.0 && r < r_prev) {
+            const double per = std::log(r / r_prev) / (double)ran;  // log decay per interval
+            const double left = std::log(tol / r) / per;
+            next = (int)std::min<double>(kRunBatchMax, std::max(1.0, 0.5 * left));
+        } else if (tol <= 0.0) {
+            next = kRunBatchMax;
+        }
+        batch = next;
+        r_prev = r;
     }
     if (status == LBM_OK && tol > 0.0 && !converged) status = LBM_NOT_CONVERGED;
     h->last_residual = r;

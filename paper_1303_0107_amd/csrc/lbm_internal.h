@@ -104,6 +104,9 @@ struct SweepArgs {
     const UinT<T> *uin;  // inlet velocity per row
     double *uprev;     // two planes (u_x, u_y); check steps only
     double *partials;  // 4 doubles per block; check steps only
+    // Nonzero *stop (when stop is set): the run this launch belongs to has
+    // already ended on the device, and the launch changes nothing.
+    const int *stop;
     int nx, ny, pitch;
     size_t plane;
     double omega;      // 1 / tau
@@ -198,6 +201,22 @@ template <typename T>
 hipError_t launch_step_batch(const SweepArgs<T> *args, const int32_t *lat,
                              const int32_t *blocks, int n_items, bool bc, hipStream_t s);
 int64_t sweep_blocks(int nx, int ny);
+// Device control block of a run to steady state: the run's check intervals
+// are queued several at a time, and each interval's finalize step records the
+// interval's sums, counts it, and ends the run (stop = 1 converged, 2
+// unstable) so that the launches queued after it change nothing.
+constexpr int kRunBatchMax = 16;
+struct RunControl {
+    double sums[kRunBatchMax][4];
+    int stop;
+    int done;  // intervals of the current batch carried out
+};
+// Sums of interval j into ctl->sums[j] (same order as launch_finalize4), then
+// the stop decision: unstable if sums[3] != 0 or a sum is not finite, else
+// converged if tol > 0 and sqrt(num)/sqrt(den) < tol.  Does nothing once
+// ctl->stop is set.
+hipError_t launch_finalize_check(const double *partials, int64_t count, RunControl *ctl, int j,
+                                 double tol, hipStream_t s);
 hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
                             hipStream_t s);
 hipError_t launch_finalize1(const double *partials, int64_t count, double *out,

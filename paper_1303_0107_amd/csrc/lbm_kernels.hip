@@ -227,6 +227,30 @@ __global__ __launch_bounds__(256) void finalize_kernel(const double *partials,
         for (int k = 0; k < NV; ++k) out[k] = v[k];
 }
 
+// The finalize step of one check interval of a queued run (see RunControl).
+__global__ __launch_bounds__(256) void finalize_check_kernel(const double *partials,
+                                                             int64_t count, RunControl *ctl,
+                                                             int j, double tol) {
+    if (ctl->stop) return;  // the run already ended: same value for every thread
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < count; i += 256)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += partials[i * 4 + k];
+    block_sum<4>(v, threadIdx.x, 256);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ctl->sums[j][k] = v[k];
+        ctl->done = j + 1;
+        const double num = v[0], den = v[1], bad = v[3];
+        if (bad != 0.0 || !isfinite(num) || !isfinite(den)) {
+            ctl->stop = 2;
+        } else if (tol > 0.0) {
+            const double r = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : sqrt(num) / sqrt(den);
+            if (r < tol) ctl->stop = 1;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Moments of the stored state (collision conserves rho and rho u, so these
 // equal the moments of the state it was relaxed from).  Optional outputs:
@@ -597,6 +621,13 @@ hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
                             hipStream_t s) {
     hipLaunchKernelGGL(finalize_kernel<4>, dim3(1), dim3(256), 0, s, partials,
                        count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_check(const double *partials, int64_t count, RunControl *ctl, int j,
+                                 double tol, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_check_kernel, dim3(1), dim3(256), 0, s, partials, count, ctl, j,
+                       tol);
     return hipGetLastError();
 }
 

@@ -196,6 +196,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
     T *L = reinterpret_cast<T *>(lds_raw);
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
+    const int halt = a.stop ? *a.stop : 0;  // read early, tested before the first barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
@@ -242,6 +243,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
             src[c][i] = L + e;
         }
     }
+    if (halt) return;  // the whole workgroup leaves: the run has ended
     __syncthreads();
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
@@ -322,6 +324,7 @@ __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T
     T *L = reinterpret_cast<T *>(lds_raw);
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
+    const int halt = a.stop ? *a.stop : 0;  // read early, tested before the first barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
@@ -358,6 +361,7 @@ __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T
     for (int c = 0; c < CPT; ++c)
 #pragma unroll
         for (int i = 0; i < 9; ++i) L[i * PL + (wave + c * NW) * RW + lane] = v[c][i];
+    if (halt) return;  // the whole workgroup leaves: the run has ended
     __syncthreads();
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
@@ -455,6 +459,7 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
     __shared__ int cls_base[H + 2];
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
+    const int halt = a.stop ? *a.stop : 0;  // read early, tested before the first barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
@@ -498,6 +503,7 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
             if (lane == 0) row_off[ry][k - 1] = __popcll(m);
         }
     }
+    if (halt) return;  // the whole workgroup leaves: the run has ended
     __syncthreads();
     if (threadIdx.x < H) {  // one thread per class: exclusive scan over rows
         const int k = threadIdx.x;
