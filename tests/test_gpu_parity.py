@@ -696,3 +696,34 @@ def test_bitwise_deterministic():
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][2], out[1][2])
+
+
+@pytest.mark.parametrize("prec,tol", [(lbm.LBM_F64, 1e-7), (lbm.LBM_F32, 3e-6)])
+def test_queued_check_intervals_stop_where_one_interval_at_a_time_stops(prec, tol):
+    """A run to steady state queues several check intervals and lets the
+    device stop it; the same solve driven one interval per call, with the
+    decision taken on the host, stops at the same step with the same state.
+    (The tolerances sit well above each form's residual floor.)"""
+    wl = I.CORRECTNESS_128x64
+    t = wl.types()
+    a = lbm.Lattice(t, wl.tau, wl.u_peak, precision=prec)
+    rc, steps, r = a.run(200000, tol, 100)
+    assert rc == lbm.LBM_OK and r < tol
+    b = lbm.Lattice(t, wl.tau, wl.u_peak, precision=prec)
+    total, rb = 0, 1.0
+    while rb >= tol:
+        _, n, rb = b.run(100, 0.0, 100)
+        total += n
+    report(f"queued intervals prec={prec}", steps=steps, r=r, r_one=rb)
+    assert steps == total
+    assert np.array_equal(a.state(), b.state())
+    # each call takes u_prev from the stored state, a run from the check step's
+    # own arithmetic: the same in FP64, within float rounding in FP32
+    assert rb == pytest.approx(r, rel=1e-6 if prec == lbm.LBM_F64 else 1e-3)
+    # without a tolerance the run goes to max_steps in full batches
+    rc, steps2, _ = a.run(1234, 0.0, 100)
+    assert rc == lbm.LBM_OK and steps2 == 1234
+    _, n2, _ = b.run(1234, 0.0, 100)
+    assert n2 == 1234 and np.array_equal(a.state(), b.state())
+    a.close()
+    b.close()
