@@ -597,7 +597,9 @@ SweepArgs<T> sweep_args(lbm_handle *h, bool check) {
     a.uin = h->uin.as<UinT<T>>();
     a.uprev = check ? h->uprev.as<double>() : nullptr;
     a.partials = check ? h->partials.as<double>() : nullptr;
-    a.stop = h->use_tb ? h->active_stop : nullptr;
+    a.stop = !h->use_tb ? nullptr
+             : h->active_stop ? h->active_stop
+                              : h->ctl.as<RunControl>()->zeros;
     a.nx = h->nx;
     a.ny = h->ny;
     a.pitch = h->pitch;
@@ -743,7 +745,7 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
         lbm_handle *h;
         ~ActiveStop() { h->active_stop = nullptr; }
     } guard{h};
-    h->active_stop = h->use_tb ? &ctl->stop : nullptr;
+    h->active_stop = h->use_tb ? ctl->stop_lanes : nullptr;
     if (h->profiling)
         for (hipEvent_t &e : h->run_ev)
             if (!e) HIP_TRY(hipEventCreate(&e));
@@ -1213,6 +1215,8 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         h->partials.ensure(std::max((size_t)sweep_blocks(h->nx, h->ny), ntiles) * 4 *
                            sizeof(double));
         h->red.ensure(64 * sizeof(double));
+        h->ctl.ensure(sizeof(RunControl));
+        HIP_TRY(hipMemsetAsync(h->ctl.p, 0, sizeof(RunControl), h->stream));
         const int n_out = (int)h->out_y0.size();
         h->out_rows.ensure(2 * (size_t)std::max(n_out, 1) * sizeof(int32_t));
         ensure_pinned(h, 64 * sizeof(double));

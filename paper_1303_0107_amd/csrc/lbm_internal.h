@@ -104,8 +104,10 @@ struct SweepArgs {
     const UinT<T> *uin;  // inlet velocity per row
     double *uprev;     // two planes (u_x, u_y); check steps only
     double *partials;  // 4 doubles per block; check steps only
-    // Nonzero *stop (when stop is set): the run this launch belongs to has
-    // already ended on the device, and the launch changes nothing.
+    // 64 copies of a flag (one per lane, so that it is read with a vector
+    // load issued beside the region's loads): nonzero when the run this
+    // launch belongs to has already ended on the device, and the launch then
+    // changes nothing.  Read by the single-lattice blocked kernels only.
     const int *stop;
     int nx, ny, pitch;
     size_t plane;
@@ -209,7 +211,9 @@ constexpr int kRunBatchMax = 16;
 struct RunControl {
     double sums[kRunBatchMax][4];
     int stop;
-    int done;  // intervals of the current batch carried out
+    int done;            // intervals of the current batch carried out
+    int stop_lanes[64];  // copies of stop, one per lane (SweepArgs::stop)
+    int zeros[64];       // SweepArgs::stop outside a queued run
 };
 // Sums of interval j into ctl->sums[j] (same order as launch_finalize4), then
 // the stop decision: unstable if sums[3] != 0 or a sum is not finite, else

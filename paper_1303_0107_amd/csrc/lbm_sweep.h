@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void step_batch_kernel(
 // distance to the region edge; 0 for solid cells) bounds the steps it can
 // take: it is advanced at step s exactly when depth >= s, and is a tile cell
 // exactly when depth >= H.
-template <class Cell, int RH, int H, int NT, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT>
 __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, const int t,
                                         const int steps, double *part_out) {
     using T = typename Cell::T;
@@ -196,8 +196,8 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
     T *L = reinterpret_cast<T *>(lds_raw);
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
-    const int halt = a.stop ? *a.stop : 0;  // read early, tested before the first barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int halt = HALT ? a.stop[lane] : 0;  // vector load beside the region's
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
 
@@ -243,7 +243,9 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
             src[c][i] = L + e;
         }
     }
-    if (halt) return;  // the whole workgroup leaves: the run has ended
+    // the whole workgroup leaves when the run has ended (the flag, read with
+    // the region, is the same for every lane)
+    if (HALT && __builtin_amdgcn_readfirstlane(halt)) return;
     __syncthreads();
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
@@ -311,7 +313,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
 // as tall fit (FP64 64 x 32: 147 KB).  Cells, depths and the order of the
 // arithmetic are those of the two-copy form, so the results are the same
 // bits.
-template <class Cell, int RH, int H, int NT, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT>
 __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T> &a,
                                                 const int t, const int steps,
                                                 double *part_out) {
@@ -324,8 +326,8 @@ __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T
     T *L = reinterpret_cast<T *>(lds_raw);
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
-    const int halt = a.stop ? *a.stop : 0;  // read early, tested before the first barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int halt = HALT ? a.stop[lane] : 0;  // vector load beside the region's
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
 
@@ -361,7 +363,9 @@ __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T
     for (int c = 0; c < CPT; ++c)
 #pragma unroll
         for (int i = 0; i < 9; ++i) L[i * PL + (wave + c * NW) * RW + lane] = v[c][i];
-    if (halt) return;  // the whole workgroup leaves: the run has ended
+    // the whole workgroup leaves when the run has ended (the flag, read with
+    // the region, is the same for every lane)
+    if (HALT && __builtin_amdgcn_readfirstlane(halt)) return;
     __syncthreads();
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
@@ -442,7 +446,7 @@ __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T
 // Each update reads the same nine values as the dense form, so the results
 // are the same bits.  LDS: the two region copies, interleaved by plane as in
 // the dense form, then PL list words.
-template <class Cell, int RH, int H, int NT, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT>
 __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T> &a, const int t,
                                                 const int steps, double *part_out) {
     using T = typename Cell::T;
@@ -459,8 +463,8 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
     __shared__ int cls_base[H + 2];
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
-    const int halt = a.stop ? *a.stop : 0;  // read early, tested before the first barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int halt = HALT ? a.stop[lane] : 0;  // vector load beside the region's
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -503,7 +507,9 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
             if (lane == 0) row_off[ry][k - 1] = __popcll(m);
         }
     }
-    if (halt) return;  // the whole workgroup leaves: the run has ended
+    // the whole workgroup leaves when the run has ended (the flag, read with
+    // the region, is the same for every lane)
+    if (HALT && __builtin_amdgcn_readfirstlane(halt)) return;
     __syncthreads();
     if (threadIdx.x < H) {  // one thread per class: exclusive scan over rows
         const int k = threadIdx.x;
@@ -618,23 +624,24 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
     }
 }
 
-// One region shape: rows x 64 cells, halo H, body KIND (TbKind).
-template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC>
+// One region shape: rows x 64 cells, halo H, body KIND (TbKind).  HALT: the
+// launch may belong to a queued run that has already ended (SweepArgs::stop).
+template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC, bool HALT>
 __device__ __forceinline__ void tb_dispatch(const SweepArgs<typename Cell::T> &a, const int t,
                                             const int steps, double *part_out) {
     if constexpr (KIND == kTbCompact)
-        tb_body_compact<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
+        tb_body_compact<Cell, RH, H, NT, CHECK, BC, HALT>(a, t, steps, part_out);
     else if constexpr (KIND == kTbInPlace)
-        tb_body_inplace<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
+        tb_body_inplace<Cell, RH, H, NT, CHECK, BC, HALT>(a, t, steps, part_out);
     else
-        tb_body<Cell, RH, H, NT, CHECK, BC>(a, t, steps, part_out);
+        tb_body<Cell, RH, H, NT, CHECK, BC, HALT>(a, t, steps, part_out);
 }
 
 template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC>
 __global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
                                                 const int32_t *__restrict__ tiles,
                                                 int steps) {
-    tb_dispatch<Cell, RH, H, NT, KIND, CHECK, BC>(
+    tb_dispatch<Cell, RH, H, NT, KIND, CHECK, BC, true>(
         a, tiles[blockIdx.x], steps, CHECK ? a.partials + (size_t)blockIdx.x * 4 : nullptr);
 }
 
@@ -648,7 +655,7 @@ __global__ __launch_bounds__(NT) void tb_batch_kernel(
     const int l = lat[blockIdx.x];
     if (l < 0) return;
     const SweepArgs<typename Cell::T> a = args[l];
-    tb_dispatch<Cell, RH, H, NT, KIND, false, BC>(a, tiles[blockIdx.x], steps, nullptr);
+    tb_dispatch<Cell, RH, H, NT, KIND, false, BC, false>(a, tiles[blockIdx.x], steps, nullptr);
 }
 
 // Dynamic LDS of one region shape.
