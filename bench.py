@@ -39,9 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # else and must be re-measured whenever the kernel changes.
 MEASURED_TRAFFIC_PER_STEP = {
     # shape 1 (32x64 dense regions, 8 steps per launch), 234 active tiles
-    ("distributor-1024x512-L3", "f32", 1): 14.915e6 / 8,
+    ("distributor-1024x512-L3", "f32", 1): 14.923e6 / 8,
     # shape 0 (32x64 compacted regions)
-    ("distributor-1024x512-L3", "f32", 0): 14.983e6 / 8,
+    ("distributor-1024x512-L3", "f32", 0): 14.982e6 / 8,
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
@@ -50,18 +50,18 @@ MEASURED_TRAFFIC_PER_LAUNCH = {
     # blocking (0: 32x64 compacted, 1: 32x64 dense, 2: 32x64 compacted with
     # 4 steps per launch, 3: 16x64 compacted, 4: 16x64 dense), 5 = one step
     # per launch
-    ("batch-256-candidates", "f32", 4, 1): 700.882e6,
+    ("batch-256-candidates", "f32", 4, 1): 700.885e6,
     ("batch-256-candidates", "f32", 4, 0): 1366.056e6,
     ("batch-256-candidates", "f32", 3, 1): 700.902e6,
     ("batch-256-candidates", "f32", 3, 0): 1366.076e6,
-    ("batch-256-candidates", "f32", 2, 1): 708.340e6,
-    ("batch-256-candidates", "f32", 2, 0): 1090.869e6,
-    ("batch-256-candidates", "f32", 1, 1): 709.159e6,
-    ("batch-256-candidates", "f32", 1, 0): 1556.351e6,
-    ("batch-256-candidates", "f32", 0, 1): 709.210e6,
-    ("batch-256-candidates", "f32", 0, 0): 1556.443e6,
-    ("batch-256-candidates", "f32", 5, 1): 684.529e6,
-    ("batch-256-candidates", "f32", 5, 0): 775.513e6,
+    ("batch-256-candidates", "f32", 2, 1): 708.338e6,
+    ("batch-256-candidates", "f32", 2, 0): 1090.860e6,
+    ("batch-256-candidates", "f32", 1, 1): 709.156e6,
+    ("batch-256-candidates", "f32", 1, 0): 1556.346e6,
+    ("batch-256-candidates", "f32", 0, 1): 709.214e6,
+    ("batch-256-candidates", "f32", 0, 0): 1556.404e6,
+    ("batch-256-candidates", "f32", 5, 1): 684.539e6,
+    ("batch-256-candidates", "f32", 5, 0): 775.523e6,
 }
 
 
