@@ -524,11 +524,38 @@ void tilings_flip(lbm_handle *h, const std::vector<int32_t> &removed,
     }
 }
 
+// Workgroup g of a launch runs on XCD g mod 8, and each XCD has its own L2.
+// The tiles are put in Z order (tile row and column bits interleaved) and
+// each XCD is dealt one contiguous run of that order, so that tiles whose
+// regions overlap (the halo cells) mostly read them through the same L2.
+std::vector<int32_t> dealt_tiles(const std::vector<int32_t> &list) {
+    auto spread = [](uint32_t v) {  // bit i of v to bit 2i
+        v &= 0xffffu;
+        v = (v | (v << 8)) & 0x00ff00ffu;
+        v = (v | (v << 4)) & 0x0f0f0f0fu;
+        v = (v | (v << 2)) & 0x33333333u;
+        v = (v | (v << 1)) & 0x55555555u;
+        return v;
+    };
+    std::vector<std::pair<uint32_t, int32_t>> z;
+    z.reserve(list.size());
+    for (int32_t t : list)
+        z.push_back({(spread((uint32_t)t >> 16) << 1) | spread((uint32_t)t & 0xffffu), t});
+    std::sort(z.begin(), z.end());
+    const size_t n = z.size(), base = n / 8, extra = n % 8;
+    std::vector<int32_t> out(n);
+    for (size_t g = 0; g < n; ++g) {
+        const size_t k = g % 8, j = g / 8;  // XCD k's j-th workgroup
+        out[g] = z[k * base + std::min(k, extra) + j].second;
+    }
+    return out;
+}
+
 // Tiles of the temporal-blocking sweep (current shape) whose cells include a
-// non-solid one, uploaded to the device.
+// non-solid one, in launch order, uploaded to the device.
 void rebuild_tiles(lbm_handle *h) {
-    h->tile_host = tile_list(h, tile_width(h->precision, h->tb_variant),
-                             tile_height(h->precision, h->tb_variant));
+    h->tile_host = dealt_tiles(tile_list(h, tile_width(h->precision, h->tb_variant),
+                                         tile_height(h->precision, h->tb_variant)));
     h->n_tiles = (int)h->tile_host.size();
     const size_t cap = max_tile_count(h->nx, h->ny, h->precision);
     h->tiles.ensure(cap * sizeof(int32_t));
