@@ -39,20 +39,20 @@ HBM_PEAK_GBS = 8000.0
 # else and must be re-measured whenever the kernel changes.
 MEASURED_TRAFFIC_PER_STEP = {
     # shape 1 (32x64 dense regions, 8 steps per launch), 234 active tiles
-    ("distributor-1024x512-L3", "f32", 1): 9.362e6 / 8,
+    ("distributor-1024x512-L3", "f32", 1): 8.420e6 / 8,
     # shape 0 (32x64 compacted regions)
-    ("distributor-1024x512-L3", "f32", 0): 9.419e6 / 8,
+    ("distributor-1024x512-L3", "f32", 0): 8.479e6 / 8,
     # profiles/sweep_tb_double_distributor-1024x512.txt: shape 0 (16x64
     # compacted, 4 steps per launch), shape 1 (16x64 dense)
-    ("distributor-1024x512-L3", "f64", 0): 14.023e6 / 4,
-    ("distributor-1024x512-L3", "f64", 1): 14.020e6 / 4,
+    ("distributor-1024x512-L3", "f64", 0): 13.140e6 / 4,
+    ("distributor-1024x512-L3", "f64", 1): 13.135e6 / 4,
     # profiles/sweep_tb_float_channel-1024x512.txt: shape 4 (16x64 dense, 4
     # steps per launch), shape 3 (16x64 compacted), shapes 1 and 0 (32x64
     # dense and compacted, 8 steps per launch)
-    ("channel-1024x512", "f32", 4): 42.175e6 / 4,
-    ("channel-1024x512", "f32", 3): 42.117e6 / 4,
-    ("channel-1024x512", "f32", 1): 45.136e6 / 8,
-    ("channel-1024x512", "f32", 0): 45.295e6 / 8,
+    ("channel-1024x512", "f32", 4): 41.019e6 / 4,
+    ("channel-1024x512", "f32", 3): 41.042e6 / 4,
+    ("channel-1024x512", "f32", 1): 43.187e6 / 8,
+    ("channel-1024x512", "f32", 0): 43.255e6 / 8,
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).

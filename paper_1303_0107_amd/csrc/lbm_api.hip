@@ -525,28 +525,15 @@ void tilings_flip(lbm_handle *h, const std::vector<int32_t> &removed,
 }
 
 // Workgroup g of a launch runs on XCD g mod 8, and each XCD has its own L2.
-// The tiles are put in Z order (tile row and column bits interleaved) and
-// each XCD is dealt one contiguous run of that order, so that tiles whose
-// regions overlap (the halo cells) mostly read them through the same L2.
+// Each XCD is dealt one contiguous run of the row-major tile list (a band of
+// tile rows), so that tiles whose regions overlap (the halo cells) mostly
+// read them through the same L2.
 std::vector<int32_t> dealt_tiles(const std::vector<int32_t> &list) {
-    auto spread = [](uint32_t v) {  // bit i of v to bit 2i
-        v &= 0xffffu;
-        v = (v | (v << 8)) & 0x00ff00ffu;
-        v = (v | (v << 4)) & 0x0f0f0f0fu;
-        v = (v | (v << 2)) & 0x33333333u;
-        v = (v | (v << 1)) & 0x55555555u;
-        return v;
-    };
-    std::vector<std::pair<uint32_t, int32_t>> z;
-    z.reserve(list.size());
-    for (int32_t t : list)
-        z.push_back({(spread((uint32_t)t >> 16) << 1) | spread((uint32_t)t & 0xffffu), t});
-    std::sort(z.begin(), z.end());
-    const size_t n = z.size(), base = n / 8, extra = n % 8;
+    const size_t n = list.size(), base = n / 8, extra = n % 8;
     std::vector<int32_t> out(n);
     for (size_t g = 0; g < n; ++g) {
         const size_t k = g % 8, j = g / 8;  // XCD k's j-th workgroup
-        out[g] = z[k * base + std::min(k, extra) + j].second;
+        out[g] = list[k * base + std::min(k, extra) + j];
     }
     return out;
 }
