@@ -525,24 +525,36 @@ void tilings_flip(lbm_handle *h, const std::vector<int32_t> &removed,
 }
 
 // Workgroup g of a launch runs on XCD g mod 8, and each XCD has its own L2.
-// Each XCD is dealt one contiguous run of the row-major tile list (a band of
-// tile rows), so that tiles whose regions overlap (the halo cells) mostly
-// read them through the same L2.
-std::vector<int32_t> dealt_tiles(const std::vector<int32_t> &list) {
-    const size_t n = list.size(), base = n / 8, extra = n % 8;
-    std::vector<int32_t> out(n);
-    for (size_t g = 0; g < n; ++g) {
-        const size_t k = g % 8, j = g / 8;  // XCD k's j-th workgroup
-        out[g] = list[k * base + std::min(k, extra) + j];
+// The row-major tile list is cut into `runs` contiguous runs (a multiple of
+// 8, sizes differing by at most one) and XCD k takes runs k, k + 8, ...:
+// tiles whose regions overlap (the halo cells) then mostly read them through
+// the same L2.  Measured: one run per XCD (bands of tile rows) is fastest
+// for the two-copy bodies; the in-place body is fastest with 32 runs, its
+// densest tiles spread over the XCDs.
+std::vector<int32_t> dealt_tiles(const std::vector<int32_t> &list, size_t runs) {
+    const size_t n = list.size(), rb = n / runs, re = n % runs;
+    std::vector<std::vector<int32_t>> xcd(8);
+    size_t at = 0;
+    for (size_t r = 0; r < runs; ++r) {
+        const size_t len = rb + (r < re ? 1 : 0);
+        xcd[r % 8].insert(xcd[r % 8].end(), list.begin() + at, list.begin() + at + len);
+        at += len;
     }
+    // XCD sizes differ by at most one, the larger ones first: slots 8j + k
+    // cover [0, n) exactly
+    std::vector<int32_t> out(n);
+    for (size_t k = 0; k < 8; ++k)
+        for (size_t j = 0; j < xcd[k].size(); ++j) out[8 * j + k] = xcd[k][j];
     return out;
 }
 
 // Tiles of the temporal-blocking sweep (current shape) whose cells include a
 // non-solid one, in launch order, uploaded to the device.
 void rebuild_tiles(lbm_handle *h) {
+    const bool inplace = tb_shape(h->precision, h->tb_variant).kind == kTbInPlace;
     h->tile_host = dealt_tiles(tile_list(h, tile_width(h->precision, h->tb_variant),
-                                         tile_height(h->precision, h->tb_variant)));
+                                         tile_height(h->precision, h->tb_variant)),
+                               inplace ? 32 : 8);
     h->n_tiles = (int)h->tile_host.size();
     const size_t cap = max_tile_count(h->nx, h->ny, h->precision);
     h->tiles.ensure(cap * sizeof(int32_t));
