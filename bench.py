@@ -42,8 +42,10 @@ MEASURED_TRAFFIC_PER_STEP = {
     ("distributor-1024x512-L3", "f32", 1): 8.420e6 / 8,
     # shape 0 (32x64 compacted regions)
     ("distributor-1024x512-L3", "f32", 0): 8.479e6 / 8,
-    # profiles/sweep_tb_double_distributor-1024x512.txt: shape 0 (16x64
-    # compacted, 4 steps per launch), shape 1 (16x64 dense)
+    # profiles/sweep_tb_double_distributor-1024x512.txt: shape 3 (32x64 in
+    # place, 8 steps per launch), shape 0 (16x64 compacted, 4 steps per
+    # launch), shape 1 (16x64 dense)
+    ("distributor-1024x512-L3", "f64", 3): 18.724e6 / 8,
     ("distributor-1024x512-L3", "f64", 0): 13.140e6 / 4,
     ("distributor-1024x512-L3", "f64", 1): 13.135e6 / 4,
     # profiles/sweep_tb_float_channel-1024x512.txt: shape 4 (16x64 dense, 4
