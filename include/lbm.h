@@ -286,7 +286,11 @@ enum { LBM_TB_DENSE = 0, LBM_TB_COMPACT = 1, LBM_TB_INPLACE = 2 };
 int lbm_tb_variant_kind(int32_t precision, int32_t variant, int32_t *kind,
                         int32_t *lds_bytes);
 
-/* Use region shape `variant` for the handle's sweeps from now on.
+/* Use region shape `variant` for the handle's sweeps from now on.  A launch
+ * covers the tiles holding a non-solid cell, dealt to the chip's eight XCDs
+ * in contiguous runs of the row-major tile list (one run per XCD for the
+ * two-copy bodies, 32 runs for the in-place body); the order changes timing
+ * only, never results.
  * Errors: LBM_EINVAL (NULL handle, variant out of range), LBM_EHIP. */
 int lbm_set_tb_variant(lbm_handle *h, int32_t variant);
 
