@@ -38,6 +38,8 @@ HBM_PEAK_GBS = 8000.0
 # (workload, storage precision, region shape); reported as null for anything
 # else and must be re-measured whenever the kernel changes.
 MEASURED_TRAFFIC_PER_STEP = {
+    # shape 5 (32x64 dense regions, 9 steps per launch), 236 active tiles
+    ("distributor-1024x512-L3", "f32", 5): 8.490e6 / 9,
     # shape 1 (32x64 dense regions, 8 steps per launch), 234 active tiles
     ("distributor-1024x512-L3", "f32", 1): 8.420e6 / 8,
     # shape 0 (32x64 compacted regions)
@@ -59,10 +61,10 @@ MEASURED_TRAFFIC_PER_STEP = {
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
 MEASURED_TRAFFIC_PER_LAUNCH = {
-    # profiles/sweep_batch_float_batch-256-candidates.txt; shapes 0..4 temporal
+    # profiles/sweep_batch_float_batch-256-candidates.txt; shapes 0..5 temporal
     # blocking (0: 32x64 compacted, 1: 32x64 dense, 2: 32x64 compacted with
-    # 4 steps per launch, 3: 16x64 compacted, 4: 16x64 dense), 5 = one step
-    # per launch
+    # 4 steps per launch, 3: 16x64 compacted, 4: 16x64 dense, 5: 32x64 dense
+    # with 9 steps per launch), 6 = one step per launch
     ("batch-256-candidates", "f32", 4, 1): 700.885e6,
     ("batch-256-candidates", "f32", 4, 0): 1366.056e6,
     ("batch-256-candidates", "f32", 3, 1): 700.902e6,
@@ -73,8 +75,10 @@ MEASURED_TRAFFIC_PER_LAUNCH = {
     ("batch-256-candidates", "f32", 1, 0): 1556.346e6,
     ("batch-256-candidates", "f32", 0, 1): 709.214e6,
     ("batch-256-candidates", "f32", 0, 0): 1556.404e6,
-    ("batch-256-candidates", "f32", 5, 1): 684.539e6,
-    ("batch-256-candidates", "f32", 5, 0): 775.523e6,
+    ("batch-256-candidates", "f32", 5, 1): 708.558e6,
+    ("batch-256-candidates", "f32", 5, 0): 1637.078e6,
+    ("batch-256-candidates", "f32", 6, 1): 684.539e6,
+    ("batch-256-candidates", "f32", 6, 0): 775.523e6,
 }
 
 

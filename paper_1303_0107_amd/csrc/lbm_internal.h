@@ -167,12 +167,10 @@ struct TbVariants<double> {
 };
 template <>
 struct TbVariants<float> {
-    static constexpr int count = 5;
-    static constexpr TbVariant v[5] = {{32, 8, kTbCompact},
-                                       {32, 8, kTbDense},
-                                       {32, 4, kTbCompact},
-                                       {16, 4, kTbCompact},
-                                       {16, 4, kTbDense}};
+    static constexpr int count = 6;
+    static constexpr TbVariant v[6] = {{32, 8, kTbCompact}, {32, 8, kTbDense},
+                                       {32, 4, kTbCompact}, {16, 4, kTbCompact},
+                                       {16, 4, kTbDense},   {32, 9, kTbDense}};
 };
 template <>
 struct TbVariants<h16> : TbVariants<float> {};
