@@ -366,6 +366,13 @@ struct lbm_handle {
     hipEvent_t tile_copied = nullptr;  // recorded after the last upload
     int n_tiles = 0;
     int tb_variant = 0;         // region shape (index into the compiled shapes)
+    // Per-shape ms/step of the last lbm_autotune (empty before one), whether
+    // its choice then had every tile resident at once, and the device's CU
+    // count and LDS per CU (how many workgroups of a shape run at once).
+    std::vector<double> tune_ms;
+    bool tune_fit = false;
+    int cus = 0;
+    size_t lds_per_cu = 0;
     uint64_t mask_version = 0;  // bumped whenever the mask changes
     // Non-solid cell counts per tile of a tw x th tiling and the tiles that
     // hold one, row-major, packed (tile row << 16 | tile column); built once
@@ -429,6 +436,13 @@ int tile_height(int precision, int variant) {
     return v.rows - 2 * v.halo;
 }
 int steps_per_launch(int precision, int variant) { return tb_shape(precision, variant).halo; }
+// LDS of one workgroup of a shape: the region copies (one when updated in
+// place) plus the compacted list.
+size_t shape_lds_bytes(int precision, int variant) {
+    const TbVariant v = tb_shape(precision, variant);
+    return (v.kind == kTbInPlace ? 1 : 2) * 9 * 64 * (size_t)v.rows * elem_size(precision) +
+           (v.kind == kTbCompact ? 64 * (size_t)v.rows * 4 : 0);
+}
 size_t tile_count(int nx, int ny, int precision, int variant) {
     const int w = tile_width(precision, variant), hh = tile_height(precision, variant);
     return (size_t)((nx + w - 1) / w) * ((ny + hh - 1) / hh);
@@ -575,6 +589,35 @@ void rebuild_tiles(lbm_handle *h) {
                                hipMemcpyHostToDevice, h->stream));
     }
     HIP_TRY(hipEventRecord(h->tile_copied, h->stream));
+}
+
+// Tiles of shape `variant` the device runs at once (one round of workgroups).
+size_t resident_tiles(const lbm_handle *h, int variant) {
+    const size_t lds = shape_lds_bytes(h->precision, variant);
+    return (size_t)h->cus * std::max<size_t>(1, h->lds_per_cu / std::max<size_t>(lds, 1));
+}
+
+// The autotuner's timings hold while its shape's tiles all run in one round.
+// When an exchange step has pushed them past that, take the fastest timed
+// shape whose tiles still fit (the shape never changes results).
+void refit_shape(lbm_handle *h) {
+    const int nv = (int)h->tune_ms.size();
+    if (nv == 0 || !h->use_tb || !h->tune_fit) return;
+    if ((size_t)h->n_tiles <= resident_tiles(h, h->tb_variant)) return;
+    std::vector<int> order(nv);
+    for (int v = 0; v < nv; ++v) order[v] = v;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return h->tune_ms[a] < h->tune_ms[b]; });
+    for (int v : order) {
+        const size_t n = tile_list(h, tile_width(h->precision, v), tile_height(h->precision, v)).size();
+        if (n <= resident_tiles(h, v)) {
+            if (v != h->tb_variant) {
+                h->tb_variant = v;
+                rebuild_tiles(h);
+            }
+            return;
+        }
+    }
 }
 
 // Parabolic inlet profile (Sec. 3.3) on each maximal run of inlet rows,
@@ -1220,6 +1263,11 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         const char *tb = std::getenv("LBM_TB");
         h->use_tb = !(tb && tb[0] == '0');
         HIP_TRY(hipGetDevice(&h->device));
+        HIP_TRY(hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device));
+        int lds = 0;
+        HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                      h->device));
+        h->lds_per_cu = (size_t)lds;
         if (cell_types) {
             if (!check_types(h->nx, h->ny, cell_types, why)) {
                 delete h;
@@ -1555,6 +1603,7 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
         if (keff > 0) {
             tilings_flip(h, rem, add);
             rebuild_tiles(h);
+            refit_shape(h);
             ++h->mask_version;
         }
         r->k_eff = (int32_t)keff;
@@ -1676,10 +1725,7 @@ int lbm_tb_variant_kind(int32_t precision, int32_t variant, int32_t *kind,
     const TbVariant v = tb_shape(precision, variant);
     if (kind) *kind = v.kind;
     // the region copies (one when updated in place), plus the compacted list
-    if (lds_bytes)
-        *lds_bytes = (int32_t)((v.kind == kTbInPlace ? 1 : 2) * 9 * 64 * (size_t)v.rows *
-                                   elem_size(precision) +
-                               (v.kind == kTbCompact ? 64 * (size_t)v.rows * 4 : 0));
+    if (lds_bytes) *lds_bytes = (int32_t)shape_lds_bytes(precision, variant);
     return LBM_OK;
 }
 
@@ -1712,6 +1758,7 @@ int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *best, double *ms,
         save_state(h, sv);
         int bv = h->tb_variant;
         double bms = INFINITY;
+        std::vector<double> times(nv);
         for (int v = 0; v < nv; ++v) {
             h->tb_variant = v;
             rebuild_tiles(h);
@@ -1719,6 +1766,7 @@ int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *best, double *ms,
                 return time_handle_steps<decltype(x)>(h, trial_steps);
             });
             restore_state(h, sv);
+            times[v] = t;
             if (ms) ms[v] = t;
             if (t < bms) {
                 bms = t;
@@ -1727,6 +1775,8 @@ int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *best, double *ms,
         }
         h->tb_variant = bv;
         rebuild_tiles(h);
+        h->tune_ms = times;
+        h->tune_fit = (size_t)h->n_tiles <= resident_tiles(h, bv);
         HIP_TRY(hipStreamSynchronize(h->stream));
         if (best) *best = bv;
     } catch (const HipFail &e) {
