@@ -303,6 +303,10 @@ int lbm_set_tb_variant(lbm_handle *h, int32_t variant);
  *   best  receives the chosen shape (may be NULL).
  *   ms    receives the mean time per step of each shape (ms_cap entries;
  *         may be NULL when ms_cap is 0).
+ * The timings are kept: if a later lbm_shape_update leaves the chosen
+ * shape with more active tiles than the device runs in one round (when the
+ * choice had them all in one), the handle moves to the fastest timed shape
+ * whose tiles still fit.
  * Errors: LBM_EINVAL (NULL handle, trial_steps < 1, ms_cap below the shape
  * count while ms is not NULL), LBM_ENOMEM, LBM_EHIP.
  */
