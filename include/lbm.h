@@ -306,7 +306,7 @@ int lbm_set_tb_variant(lbm_handle *h, int32_t variant);
  * The timings are kept: if a later lbm_shape_update leaves the chosen
  * shape with more active tiles than the device runs in one round (when the
  * choice had them all in one), the handle moves to the fastest timed shape
- * whose tiles still fit.
+ * whose tiles still fit.  lbm_set_tb_variant drops the kept timings.
  * Errors: LBM_EINVAL (NULL handle, trial_steps < 1, ms_cap below the shape
  * count while ms is not NULL), LBM_ENOMEM, LBM_EHIP.
  */

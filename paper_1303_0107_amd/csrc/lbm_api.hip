@@ -1737,6 +1737,7 @@ int lbm_set_tb_variant(lbm_handle *h, int32_t variant) {
     try {
         HIP_TRY(hipSetDevice(h->device));
         h->tb_variant = variant;
+        h->tune_ms.clear();  // an explicit choice is kept through exchange steps
         rebuild_tiles(h);
     } catch (const HipFail &e) {
         return guard_hip(e);
