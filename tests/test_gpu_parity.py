@@ -648,6 +648,38 @@ def test_graph_replay_matches_direct_launches(prec, monkeypatch):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("shape", [(65536, 6), (8, 65536)])
+def test_longest_side_every_shape_and_the_oracle(prec, shape, monkeypatch):
+    """Channels with the longest side the library accepts (65536 cells), so
+    tile and block coordinates reach their largest values: every compiled
+    region shape gives the bits of one launch per step, and those match the
+    oracle (bit for bit in FP64, within tolerance in FP32)."""
+    nx, ny = shape
+    t = I.channel(nx, ny)
+    steps = 23
+    print(f"longest side {nx}x{ny} prec={prec}", flush=True)
+    monkeypatch.setenv("LBM_TB", "0")
+    g = lbm.Lattice(t, 0.7, 0.04, precision=prec)
+    g.run(steps, 0.0, steps)
+    ref = g.state()
+    ref_macro = g.macro()
+    g.close()
+    monkeypatch.setenv("LBM_TB", "1")
+    for v in range(lbm.lbm_tb_variant_count(prec)):
+        g = lbm.Lattice(t, 0.7, 0.04, precision=prec)
+        g.set_tb_variant(v)
+        g.run(steps, 0.0, steps)
+        assert np.array_equal(g.state(), ref), f"shape {v}"
+        g.close()
+    o = oracle.Lattice(t, 0.7, 0.04)
+    o.run(steps, 0.0, steps)
+    if prec == lbm.LBM_F64:
+        assert np.array_equal(ref, o.fs)
+    else:
+        assert fields_ok(t, ref_macro, o.macro(), TOL[prec], f"longest side {nx}x{ny}")
+
+
 @pytest.mark.parametrize("prec", ALL)
 @pytest.mark.parametrize("shape", [(200, 70), (130, 37)])
 def test_temporal_blocking_matches_single_steps(prec, shape, monkeypatch):
