@@ -32,31 +32,35 @@ if ROOT not in sys.path:
 METRIC = "MLUPS + % HBM roofline (D2Q9 1024x512); p50/p99 solve latency, mixed load"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per time step of the plain sweep launches, from rocprofv3
-# FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of known size) of this
-# build's kernels; profiles/sweep_tb_float_distributor-1024x512.txt.  Keyed by
+# HBM bytes of one full launch (halo = steps per launch) of the blocked
+# sweep, from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a plain copy of
+# known size) of this build's kernels; profiles/sweep_tb_*.txt.  Keyed by
 # (workload, storage precision, region shape); reported as null for anything
-# else and must be re-measured whenever the kernel changes.
-MEASURED_TRAFFIC_PER_STEP = {
+# else and must be re-measured whenever the kernel changes.  A launch moves
+# about the same bytes whatever its step count (it loads its region and
+# stores its tile once), and the last launch of each check interval also
+# reads and writes u_prev (two FP64 planes, 32 B per non-solid cell), so the
+# reported traffic per launch is full + 32 B * N_ns / (launches per interval).
+MEASURED_TRAFFIC_PER_FULL_LAUNCH = {
     # shape 5 (32x64 dense regions, 9 steps per launch), 236 active tiles
-    ("distributor-1024x512-L3", "f32", 5): 8.490e6 / 9,
+    ("distributor-1024x512-L3", "f32", 5): 8.490e6,
     # shape 1 (32x64 dense regions, 8 steps per launch), 234 active tiles
-    ("distributor-1024x512-L3", "f32", 1): 8.420e6 / 8,
+    ("distributor-1024x512-L3", "f32", 1): 8.420e6,
     # shape 0 (32x64 compacted regions)
-    ("distributor-1024x512-L3", "f32", 0): 8.479e6 / 8,
+    ("distributor-1024x512-L3", "f32", 0): 8.479e6,
     # profiles/sweep_tb_double_distributor-1024x512.txt: shape 3 (32x64 in
     # place, 8 steps per launch), shape 0 (16x64 compacted, 4 steps per
     # launch), shape 1 (16x64 dense)
-    ("distributor-1024x512-L3", "f64", 3): 18.724e6 / 8,
-    ("distributor-1024x512-L3", "f64", 0): 13.140e6 / 4,
-    ("distributor-1024x512-L3", "f64", 1): 13.135e6 / 4,
+    ("distributor-1024x512-L3", "f64", 3): 18.724e6,
+    ("distributor-1024x512-L3", "f64", 0): 13.140e6,
+    ("distributor-1024x512-L3", "f64", 1): 13.135e6,
     # profiles/sweep_tb_float_channel-1024x512.txt: shape 4 (16x64 dense, 4
     # steps per launch), shape 3 (16x64 compacted), shapes 1 and 0 (32x64
     # dense and compacted, 8 steps per launch)
-    ("channel-1024x512", "f32", 4): 41.019e6 / 4,
-    ("channel-1024x512", "f32", 3): 41.042e6 / 4,
-    ("channel-1024x512", "f32", 1): 43.187e6 / 8,
-    ("channel-1024x512", "f32", 0): 43.255e6 / 8,
+    ("channel-1024x512", "f32", 4): 41.019e6,
+    ("channel-1024x512", "f32", 3): 41.042e6,
+    ("channel-1024x512", "f32", 1): 43.187e6,
+    ("channel-1024x512", "f32", 0): 43.255e6,
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
@@ -461,8 +465,9 @@ def main() -> int:
     n, res, flow, st, r = last
     spread = float((flow.max() - flow.min()) / flow.mean()) if len(flow) else 0.0
     kernel = "tb_kernel" if steps_per_launch > 1.0 else "step_kernel"
-    per_step = MEASURED_TRAFFIC_PER_STEP.get((w.name, args.precision, shape))
-    traffic = round(per_step * steps_per_launch) if per_step else None
+    full = MEASURED_TRAFFIC_PER_FULL_LAUNCH.get((w.name, args.precision, shape))
+    per_interval = -(-k // halo)  # launches per check interval
+    traffic = round(full + 32 * nns / per_interval) if full else None
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),

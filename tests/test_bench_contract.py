@@ -36,10 +36,10 @@ def test_cpu_baseline_fields():
 
 def test_measured_traffic_names_compiled_shapes():
     names = set(bench.workloads())
-    for (workload, prec, shape), per_step in bench.MEASURED_TRAFFIC_PER_STEP.items():
+    for (workload, prec, shape), full in bench.MEASURED_TRAFFIC_PER_FULL_LAUNCH.items():
         assert workload in names
         assert 0 <= shape < lbm.lbm_tb_variant_count(PREC[prec])
-        assert per_step > 0
+        assert full > 0
     for (workload, prec, shape, order), per_launch in bench.MEASURED_TRAFFIC_PER_LAUNCH.items():
         assert workload == bench.BATCH_WORKLOAD
         assert 0 <= shape <= lbm.lbm_tb_variant_count(PREC[prec])  # count = one step per launch
