@@ -9,6 +9,7 @@ GPU package never imports it.
 Function map (paper passages):
   equilibrium, collide_cell ... Sec. 2.1, Eq. 1 and the equilibrium below it
   run_to_steady ............... Sec. 2.3 steps (2)/(4) (one LBM solve)
+  residual .................... Sec. 2.3 step (2) (the steady-state test)
   macro ....................... Eq. 2
   outlet_stats ................ Eq. 4, Eqs. 9-11
   shape_update ................ Sec. 2.2 (Eqs. 5, 6), Sec. 2.3 step (3)
@@ -77,6 +78,8 @@ def _load():
         lib.orc_shape_update.argtypes = [i32, i32, P, P, P, P, f64, u64, i32, i32, i32, i32,
                                          P, P, P, i32, P, P, P, P]
         lib.orc_num_threads.restype = i32
+        lib.orc_residual.argtypes = [i32, i32, P, P, P, P, P]
+        lib.orc_residual.restype = f64
         _lib = lib
     return _lib
 
@@ -119,6 +122,17 @@ def splitmix64(state: int) -> int:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def residual(types: np.ndarray, ux, uy, ux_prev, uy_prev) -> float:
+    """r = ||u - u_prev|| / ||u|| over the non-solid cells (Sec. 2.3 step 2)."""
+    t = np.ascontiguousarray(types, np.uint8)
+    ny, nx = t.shape
+    a = [np.ascontiguousarray(v, np.float64) for v in (ux, uy, ux_prev, uy_prev)]
+    for v in a:
+        if v.shape != t.shape:
+            raise ValueError("fields must have the shape of the type map")
+    return float(_load().orc_residual(nx, ny, _ptr(t), *(_ptr(v) for v in a)))
 
 
 def inlet_profile(types: np.ndarray, u_peak: float, flags: int = 0) -> np.ndarray:

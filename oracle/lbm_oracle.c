@@ -314,12 +314,14 @@ static void collide_pass(int nx, int ny, const uint8_t *type, const double *f,
     }
 }
 
-/* Residual r = ||u - u_prev||_2 / ||u||_2 over non-solid cells, summed
- * sequentially in row-major order.  A zero denominator gives 0 when the
- * numerator is zero too, +inf otherwise. */
-static double residual(int nx, int ny, const uint8_t *type, const double *ux,
-                       const double *uy, const double *pux,
-                       const double *puy) {
+/* Residual r = ||u - u_prev||_2 / ||u||_2 over non-solid cells (the
+ * steady-state test of Sec. 2.3 step (2): the flow field has stopped
+ * changing), summed sequentially in row-major order.  A zero denominator
+ * gives 0 when the numerator is zero too, +inf otherwise.  Exported so that
+ * the tests can pin it on fields with a closed-form answer; orc_run_ex uses
+ * this same function. */
+double orc_residual(int nx, int ny, const uint8_t *type, const double *ux,
+                    const double *uy, const double *pux, const double *puy) {
     const size_t N = (size_t)nx * ny;
     double num = 0.0, den = 0.0;
     for (size_t n = 0; n < N; ++n) {
@@ -416,7 +418,7 @@ int orc_run_ex(int nx, int ny, const uint8_t *type, double tau, double u_peak,
             res = NAN;
             break;
         }
-        res = residual(nx, ny, type, ux, uy, pux, puy);
+        res = orc_residual(nx, ny, type, ux, uy, pux, puy);
         memcpy(pux, ux, sizeof(double) * N);
         memcpy(puy, uy, sizeof(double) * N);
         if (tol > 0.0 && res < tol) break;

@@ -308,3 +308,120 @@ def test_splitmix64_published_vector(orc):
     gamma = 0x9E3779B97F4A7C15
     assert orc.splitmix64(gamma) == 0x6E789E6AA1B965F4
     assert orc.splitmix64((2 * gamma) % 2 ** 64) == 0x06C45D188009454F
+
+
+# ---------------------------------------------------------------- residual
+def _box_types():
+    t = I.closed_box(12, 9, obstacles=6, seed=2)
+    assert (t != 0).sum() > 20
+    return t
+
+
+def test_residual_uniform_fields_closed_form(orc):
+    """Sec. 2.3 step (2): the flow field has stopped changing when
+    r = ||u - u_prev||_2 / ||u||_2 is small.  With u and u_prev uniform over
+    the non-solid cells, r = |u - u_prev| / |u| whatever the cell count; the
+    values below are exact binary fractions, so r is known to an ulp.  A
+    squared ratio (0.769...) or a division by ||u_prev|| (1.414...) would
+    fail."""
+    t = _box_types()
+    ns = t != 0
+    ux = np.where(ns, 0.75, 0.0)
+    uy = np.where(ns, -0.5, 0.0)
+    px = np.where(ns, 0.5, 0.0)
+    py = np.where(ns, 0.25, 0.0)
+    expect = math.sqrt((0.25 ** 2 + 0.75 ** 2) / (0.75 ** 2 + 0.5 ** 2))
+    assert orc.residual(t, ux, uy, px, py) == pytest.approx(expect, rel=4e-16)
+
+
+def test_residual_two_cells_and_solid_cells_ignored(orc):
+    """u = (1, 0), (0, 2) against u_prev = (0, 0), (0, 2) on two fluid cells:
+    numerator 1, denominator 1 + 4, r = 1/sqrt(5).  Solid cells carry large
+    values that must not enter either norm."""
+    t = np.zeros((3, 4), np.uint8)
+    t[1, 1] = t[1, 2] = 1
+    ux = np.full(t.shape, 7.0)
+    uy = np.full(t.shape, -9.0)
+    px = np.full(t.shape, 3.0)
+    py = np.full(t.shape, 5.0)
+    ux[1, 1], uy[1, 1], px[1, 1], py[1, 1] = 1.0, 0.0, 0.0, 0.0
+    ux[1, 2], uy[1, 2], px[1, 2], py[1, 2] = 0.0, 2.0, 0.0, 2.0
+    assert orc.residual(t, ux, uy, px, py) == pytest.approx(1 / math.sqrt(5), rel=4e-16)
+
+
+def test_residual_degenerate_fields(orc):
+    """No flow now and before: 0.  No flow now but some before: infinite."""
+    t = _box_types()
+    z = np.zeros(t.shape)
+    assert orc.residual(t, z, z, z, z) == 0.0
+    assert orc.residual(t, z, z, z + 0.1, z) == math.inf
+
+
+def test_run_reports_the_residual_of_its_last_interval(orc):
+    """orc_run_ex's residual is r between the velocity at the last check and
+    the velocity check_every steps earlier (the state passed in, for the
+    first interval): recomputed from the macroscopic fields of the two states,
+    it agrees to round-off (the run takes u from the populations before
+    relaxation, macro() from the stored ones after it)."""
+    t = I.distributor(128, 64, 2, [8, 6, 4])
+    lat = orc.Lattice(t, 0.8, 0.05)
+    lat.run(300, 0.0, 100)
+    _, ux0, uy0 = lat.macro()
+    status, steps, r = lat.run(40, 0.0, 40)
+    assert status == orc.OK and steps == 40
+    _, ux1, uy1 = lat.macro()
+    assert r == pytest.approx(orc.residual(t, ux1, uy1, ux0, uy0), rel=1e-9)
+    assert r > 1e-4  # the flow is still developing after 340 steps
+
+
+# ---------------------------------------------------------------- mass, flux
+def test_mass_and_fluxes_of_a_hand_built_state(orc):
+    """Sec. 4.2 reductions on a state whose moments are exact: all of each
+    cell's mass in f0 (a dyadic density), plus f1 = a, f3 = b on the inlet and
+    outlet cells so that rho u_x = a - b there.  Mass = sum of densities over
+    the non-solid cells; solid cells hold values that must be ignored."""
+    t = I.distributor(64, 32, 1, [6, 4])
+    ny, nx = t.shape
+    lat = orc.Lattice(t, 0.8, 0.0)
+    rng = np.random.default_rng(3)
+    rho = rng.integers(1, 64, size=(ny, nx)).astype(np.float64) / 32.0
+    fs = np.zeros((9, ny, nx))
+    fs[0] = rho
+    a, b = 0.375, 0.125
+    ports = (t == 2) | (t == 3)
+    fs[1][ports] = a
+    fs[3][ports] = b
+    fs[0][ports] -= a + b
+    fs[:, t == 0] = 1e3
+    lat.fs[:] = fs
+    s = lat.outlet_stats()
+    assert s.mass == float(rho[t != 0].sum())
+    n_in = int((t == 2).sum())
+    assert s.flow_in == n_in * (a - b)
+    counts = [int(c) for c in _run_lengths(t[:, -1] == 3)]
+    assert list(s.flow) == [c * (a - b) for c in counts]
+
+
+def _run_lengths(mask):
+    out, n = [], 0
+    for v in list(mask) + [False]:
+        if v:
+            n += 1
+        elif n:
+            out.append(n)
+            n = 0
+    return out
+
+
+@pytest.mark.parametrize("tau", [0.55, 0.8, 1.7])
+def test_collision_scales_nonequilibrium_by_one_minus_inverse_tau(orc, tau):
+    """Eq. 1: f* - feq = (1 - 1/tau)(f - feq) population by population, so a
+    relaxation rate of tau instead of 1/tau fails at every tau != 1."""
+    rng = np.random.default_rng(11)
+    cx, cy, _, w = orc.velocity_set()
+    f = w * (1 + 0.05 * rng.uniform(-1, 1, 9))
+    rho = f.sum()
+    feq = orc.equilibrium(rho, (cx * f).sum() / rho, (cy * f).sum() / rho)
+    out = orc.collide_cell(f, tau)
+    ratio = (out - feq) / (f - feq)
+    assert np.allclose(ratio, 1 - 1 / tau, rtol=0, atol=1e-11)
