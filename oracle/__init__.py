@@ -11,7 +11,10 @@ Function map (paper passages):
   run_to_steady ............... Sec. 2.3 steps (2)/(4) (one LBM solve)
   residual .................... Sec. 2.3 step (2) (the steady-state test)
   macro ....................... Eq. 2
-  outlet_stats ................ Eq. 4, Eqs. 9-11
+  outlet_stats ................ Eq. 4, Eqs. 9-11 on one stored state
+  outlet_stats2 ............... the same as steady flow rates: mean over two
+                                consecutive steps (the boundary fluxes carry an
+                                undamped period-two lattice oscillation)
   shape_update ................ Sec. 2.2 (Eqs. 5, 6), Sec. 2.3 step (3)
   tau_from_nu ................. Sec. 2.1 (tau = 3 nu + dt/2)
   flags NEUMANN_OUTLET, SYMMETRY_TOP ... Sec. 3.3 (the paper's own runs:
@@ -73,6 +76,8 @@ def _load():
         lib.orc_run_ex.argtypes = [i32, i32, P, f64, f64, f64, ctypes.c_int32, P, i64, f64,
                                    ctypes.c_int32, ctypes.c_int32, P, P]
         lib.orc_outlet_stats.argtypes = [i32, i32, P, P, P, i32, P, P, P, P, P]
+        lib.orc_outlet_stats2.argtypes = [i32, i32, P, f64, f64, f64, ctypes.c_int32, P, P,
+                                          i32, P, P, P, P, P, P]
         lib.orc_splitmix64.argtypes = [u64]
         lib.orc_splitmix64.restype = u64
         lib.orc_shape_update.argtypes = [i32, i32, P, P, P, P, f64, u64, i32, i32, i32, i32,
@@ -154,6 +159,11 @@ class Stats:
 
 
 @dataclass
+class Stats2(Stats):
+    flow_p2: float
+
+
+@dataclass
 class ShapeResult:
     k_eff: int
     removed: np.ndarray
@@ -211,6 +221,19 @@ class Lattice:
         if n < 0:
             raise ValueError(f"oracle outlet_stats failed (rc={n})")
         return Stats(flow[:n].copy(), fin.value, dp.value, th.value, dg.value, m.value)
+
+    def outlet_stats2(self, cap: int = 4096) -> Stats2:
+        """Statistics of the steady flow: the mean over this state and the
+        state one step later (the state is not changed)."""
+        flow = np.zeros(cap)
+        fin, dp, th, dg, m, p2 = (ctypes.c_double() for _ in range(6))
+        n = _load().orc_outlet_stats2(self.nx, self.ny, _ptr(self.types), self.tau, self.u_peak,
+                                      self.rho_out, self.flags, _ptr(self.fs), _ptr(flow), cap,
+                                      ctypes.byref(fin), ctypes.byref(dp), ctypes.byref(th),
+                                      ctypes.byref(dg), ctypes.byref(m), ctypes.byref(p2))
+        if n < 0:
+            raise ValueError(f"oracle outlet_stats2 failed (rc={n})")
+        return Stats2(flow[:n].copy(), fin.value, dp.value, th.value, dg.value, m.value, p2.value)
 
     def shape_update(self, frac=0.01, seed=0, band_x=2, band_y=1, criterion=CRIT_PAPER,
                      reinit=WARM, field=None) -> ShapeResult:
