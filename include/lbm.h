@@ -56,10 +56,12 @@ extern "C" {
 #define LBM_OUTLET 3
 
 /* ---- precision forms ------------------------------------------------------
- * LBM_F64:        populations f_i stored and relaxed in double precision, in
+ * LBM_F64:        populations f_i stored in double, relaxed in double, in
  *                 the reference operation order (bitwise reproducible).
- * LBM_F32:        offsets f_i - w_i stored in float, relaxed in double.
- * LBM_F32_S_F16:  offsets stored in IEEE half precision, relaxed in float.
+ * LBM_F32:        offsets f_i - w_i stored in float, relaxed in float (a
+ *                 relaxation that conserves mass and momentum exactly).
+ * LBM_F32_S_F16:  offsets stored in half (IEEE binary16, scaled by 2^12),
+ *                 relaxed in float.
  * LBM_F32_S_BF16: offsets stored in bfloat16, relaxed in float.
  * Reductions (mass, fluxes, pressure drop, residual, exchange keys) are
  * double in every form. */
@@ -67,6 +69,12 @@ extern "C" {
 #define LBM_F32 1
 #define LBM_F32_S_F16 2
 #define LBM_F32_S_BF16 3
+
+/* Bytes of one stored population value and of the floating-point type the
+ * per-cell update computes in, for a precision form (the two words after
+ * "stored in" and "relaxed in" above).  Needs no device.
+ * Errors: LBM_EINVAL (unknown form, NULL pointer). */
+int lbm_precision_info(int32_t precision, int32_t *storage_bytes, int32_t *arith_bytes);
 
 /* ---- exchange-step options --------------------------------------------- */
 #define LBM_WARM 0        /* new fluid cells start at rest, rest is kept    */
@@ -92,11 +100,12 @@ typedef struct {
 } lbm_geometry_desc;
 
 /* Boundary variants of the paper's own runs (Sec. 3.3).
- * LBM_NEUMANN_OUTLET: outlet cells take no density closure (rho_out is then
- *   unused); the populations entering an outlet cell from outside (c_x < 0)
- *   are those its neighbour at x-1 receives in the same streaming step, walls
- *   included (zero gradient across the outlet).  An outlet cell whose x-1
- *   neighbour is solid gets plain bounce-back there.
+ * LBM_NEUMANN_OUTLET: zero normal gradient of the velocity at the outlet
+ *   (Sec. 3.3; rho_out is then unused).  Each outlet cell imposes the velocity
+ *   (Eq. 2) of the stored state of its neighbour at x-1 (zero when that cell
+ *   is solid) through the Zou-He velocity closure of an east boundary: the
+ *   unknown populations 3, 6, 7 follow from that velocity and the known
+ *   populations, and the cell's density from the known populations.
  * LBM_SYMMETRY_TOP: the lattice is the lower half of a domain that is mirror
  *   symmetric about the line just above row ny-1.  A population that would be
  *   pulled from row ny is the mirror image (c_y reversed) of the one leaving
@@ -105,7 +114,9 @@ typedef struct {
  *   spans both halves). */
 enum { LBM_NEUMANN_OUTLET = 1, LBM_SYMMETRY_TOP = 2 };
 
-/* Boundary reductions of one state (Eq. 4, Eqs. 9-11). */
+/* Boundary reductions (Eq. 4, Eqs. 9-11) of the steady flow: every flux
+ * and the pressure drop are means over the current state and the state one
+ * time step later (see lbm_outlet_stats). */
 typedef struct {
     int32_t n_outlets;  /* maximal runs of outlet cells in column nx-1    */
     int32_t reserved;
@@ -119,6 +130,8 @@ typedef struct {
     double mass;        /* sum of rho over non-solid cells                 */
     double residual;    /* residual of the last lbm_run_to_steady          */
     int64_t steps;      /* time steps run since creation or set_state      */
+    double flow_p2;     /* largest period-two component of an outlet flux,
+                           max_k |flow_k(t) - flow_k(t+1)| / 2            */
 } lbm_stats;
 
 /* Parameters of one exchange step (Sec. 2.2, Sec. 2.3 step 3). */
@@ -179,10 +192,18 @@ int lbm_run_to_steady(lbm_handle *h, int64_t max_steps, double tol,
                       double *residual);
 
 /*
- * Step (5) of Sec. 2.3 and Sec. 4.2: boundary reductions of the current
- * state.  flow receives the mass flux sum(rho u_x) of each outlet, ordered by
- * increasing y (flow_cap doubles available).  All sums are double precision
- * and run in a fixed order, so repeated calls give identical bits.
+ * Step (5) of Sec. 2.3 and Sec. 4.2: boundary reductions of the steady flow.
+ * flow receives the mass flux sum(rho u_x) of each outlet, ordered by
+ * increasing y (flow_cap doubles available), as the mean of the current
+ * state's flux and that of the state one step later: converged flows carry
+ * an undamped oscillation of period two steps at the fixed-density outlets
+ * (a few percent of the outlet flux on the distributors), which the residual
+ * of lbm_run_to_steady does not see; the two-step mean cancels it.  flow_in
+ * and dp are means in the same way, theta, dg and flow_ave are taken on the
+ * mean fluxes, mass is the current state's.  The later state is computed in
+ * the handle's second population buffer; the current state is not changed.
+ * All sums are double precision and run in a fixed order, so repeated calls
+ * give identical bits.
  * Errors: LBM_EINVAL if flow_cap < n_outlets (s->n_outlets is still set), or a
  * NULL pointer; LBM_EHIP.
  */

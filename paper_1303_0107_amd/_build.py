@@ -1,6 +1,7 @@
 """Compile the HIP library liblbm.so for gfx950 (in-tree)."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import tempfile
@@ -32,17 +33,22 @@ SOURCES = {
 def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     with tempfile.TemporaryDirectory() as tmp:
-        objs = []
+        jobs = []
         for src, extra in SOURCES.items():
             obj = os.path.join(tmp, src + ".o")
             cmd = [HIPCC, *COMMON, *extra, *[f"-D{d}" for d in defines], *inc, "-c",
                    os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            res = subprocess.run(cmd, capture_output=True, text=True)
+            jobs.append((src, obj, cmd))
+        # one compiler process per source, at most four at a time
+        with concurrent.futures.ThreadPoolExecutor(max_workers=4) as pool:
+            results = list(pool.map(
+                lambda j: subprocess.run(j[2], capture_output=True, text=True), jobs))
+        for (src, _, _), res in zip(jobs, results):
             if res.returncode != 0:
                 raise RuntimeError(f"hipcc failed on {src}:\n" + res.stdout + res.stderr)
-            objs.append(obj)
+        objs = [obj for _, obj, _ in jobs]
         tmp_lib = out + ".tmp"
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_lib, *objs]
         res = subprocess.run(cmd, capture_output=True, text=True)

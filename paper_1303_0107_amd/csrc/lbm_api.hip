@@ -879,25 +879,34 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
     return status;
 }
 
+// Boundary sums of the current state and of the state one step later (a
+// single sweep into the other population buffer, which holds nothing of use
+// between steps; the current state and buffer parity are untouched), then
+// the mass of the current state.  bout: 2 * (2 n_out + 5) sums, the current
+// state's first.
 template <typename T>
 void stats_impl(lbm_handle *h, std::vector<double> &bout, double &mass) {
     const int n_out = (int)h->out_y0.size();
     const size_t nb = (size_t)(2 * n_out + 5);
-    h->bnd.ensure((nb + 1) * sizeof(double));
-    ensure_pinned(h, (nb + 1) * sizeof(double));
+    h->bnd.ensure((2 * nb + 1) * sizeof(double));
+    ensure_pinned(h, (2 * nb + 1) * sizeof(double));
     MacroArgs<T> a = macro_args<T>(h);
     double *bo = h->bnd.as<double>();
-    HIP_TRY(launch_boundary<T>(a, h->out_rows.as<int32_t>(),
-                               h->out_rows.as<int32_t>() + std::max(n_out, 1),
-                               n_out, bo, h->stream));
+    const int32_t *y0 = h->out_rows.as<int32_t>();
+    const int32_t *y1 = y0 + std::max(n_out, 1);
+    HIP_TRY(launch_boundary<T>(a, y0, y1, n_out, bo, h->stream));
+    HIP_TRY(launch_sweep<T>(sweep_args<T>(h, false), false, h->stream));
+    MacroArgs<T> next = a;
+    next.f = h->f[1 - h->cur].as<T>();
+    HIP_TRY(launch_boundary<T>(next, y0, y1, n_out, bo + nb, h->stream));
     HIP_TRY(launch_mass<T>(a, h->partials.as<double>(), h->stream));
     HIP_TRY(launch_finalize1(h->partials.as<double>(), sweep_blocks(h->nx, h->ny),
-                             bo + nb, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->pinned, bo, (nb + 1) * sizeof(double),
+                             bo + 2 * nb, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->pinned, bo, (2 * nb + 1) * sizeof(double),
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    bout.assign(h->pinned, h->pinned + nb);
-    mass = h->pinned[nb];
+    bout.assign(h->pinned, h->pinned + 2 * nb);
+    mass = h->pinned[2 * nb];
 }
 
 template <typename T>
@@ -1411,14 +1420,25 @@ int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
     } catch (const std::bad_alloc &) {
         return fail(LBM_ENOMEM, "allocation failed");
     }
-    for (int k = 0; k < n_out; ++k) flow[k] = b[k];
-    const double flow_in = b[2 * n_out], rho_in_sum = b[2 * n_out + 1];
-    const double cnt_in = b[2 * n_out + 2], cnt_out = b[2 * n_out + 3];
-    const double rho_out_sum = b[2 * n_out + 4];
-    const double rin = cnt_in > 0 ? rho_in_sum / cnt_in : 0.0;
-    const double rout = cnt_out > 0 ? rho_out_sum / cnt_out : 0.0;
-    s->flow_in = flow_in;
-    s->dp = (rin - rout) / 3.0;  // Eq. 4 with c_s^2 = 1/3
+    // The steady flow rates: means over the current state (sums b[0, nb)) and
+    // the state one step later (b[nb, 2 nb)), which cancel the undamped
+    // period-two oscillation of the boundary fluxes; Eqs. 9-11 on the means.
+    const size_t nb = (size_t)(2 * n_out + 5);
+    auto dp_of = [&](const double *c) {  // Eq. 4 with c_s^2 = 1/3
+        const double rho_in_sum = c[2 * n_out + 1], cnt_in = c[2 * n_out + 2];
+        const double cnt_out = c[2 * n_out + 3], rho_out_sum = c[2 * n_out + 4];
+        const double rin = cnt_in > 0 ? rho_in_sum / cnt_in : 0.0;
+        const double rout = cnt_out > 0 ? rho_out_sum / cnt_out : 0.0;
+        return (rin - rout) / 3.0;
+    };
+    double p2 = 0.0;
+    for (int k = 0; k < n_out; ++k) {
+        p2 = std::max(p2, std::fabs(b[k] - b[nb + k]) * 0.5);
+        flow[k] = 0.5 * (b[k] + b[nb + k]);
+    }
+    s->flow_in = 0.5 * (b[2 * n_out] + b[nb + 2 * n_out]);
+    s->dp = 0.5 * (dp_of(b.data()) + dp_of(b.data() + nb));
+    s->flow_p2 = p2;
     s->mass = mass;
     if (n_out > 0) {
         double mx = flow[0], mn = flow[0], sum = 0.0;
@@ -1703,6 +1723,18 @@ int lbm_tb_variant_kind(int32_t precision, int32_t variant, int32_t *kind,
     if (kind) *kind = v.kind;
     // the region copies (one when updated in place), plus the compacted list
     if (lds_bytes) *lds_bytes = (int32_t)shape_lds_bytes(precision, variant);
+    return LBM_OK;
+}
+
+int lbm_precision_info(int32_t precision, int32_t *storage_bytes, int32_t *arith_bytes) {
+    g_error.clear();
+    if (precision < LBM_F64 || precision > LBM_F32_S_BF16 || !storage_bytes || !arith_bytes)
+        return fail(LBM_EINVAL, "unknown precision or null pointer");
+    with_storage(precision, [&](auto t) {
+        using T = decltype(t);
+        *storage_bytes = (int32_t)sizeof(T);
+        *arith_bytes = (int32_t)sizeof(ArithT<T>);
+    });
     return LBM_OK;
 }
 

@@ -64,7 +64,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
 // f - (1/tau)(f - feq) (Eq. 1) to the equilibrium of Sec. 2.1.
 struct Cell {
     using T = double;
-    using CT = double;
+    using CT = ArithT<double>;
     __device__ static __forceinline__ double load(double v) { return v; }
     __device__ static __forceinline__ double store(double v) { return v; }
     // Velocity (Eq. 2) of a stored population set, formed as the oracle does.

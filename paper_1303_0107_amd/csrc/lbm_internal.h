@@ -95,6 +95,11 @@ struct Sto<bf16> {
 // forms (never 16-bit: the imposed velocity keeps its precision).
 template <typename T>
 using UinT = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
+// Arithmetic type of the per-cell update for a storage type: double for the
+// double form, float for every offset form.  The cell policies are built from
+// it and lbm_precision_info reports it.
+template <typename T>
+using ArithT = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
 
 template <typename T>
 struct SweepArgs {

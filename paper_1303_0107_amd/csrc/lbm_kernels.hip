@@ -208,9 +208,9 @@ struct OffsetCell {
     }
 };
 
-using F32Cell = OffsetCell<float, float, float>;
-using H16Cell = OffsetCell<h16, float, float>;
-using BF16Cell = OffsetCell<bf16, float, float>;
+using F32Cell = OffsetCell<float, ArithT<float>, float>;
+using H16Cell = OffsetCell<h16, ArithT<h16>, float>;
+using BF16Cell = OffsetCell<bf16, ArithT<bf16>, float>;
 
 // Sum `count` groups of NV doubles in a fixed order (one block of 256).
 template <int NV>

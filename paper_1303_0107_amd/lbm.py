@@ -49,7 +49,8 @@ class lbm_stats(ctypes.Structure):
                 ("flow_in", ctypes.c_double), ("dp", ctypes.c_double),
                 ("theta", ctypes.c_double), ("dg", ctypes.c_double),
                 ("flow_ave", ctypes.c_double), ("mass", ctypes.c_double),
-                ("residual", ctypes.c_double), ("steps", ctypes.c_int64)]
+                ("residual", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("flow_p2", ctypes.c_double)]
 
 
 class lbm_shape_params(ctypes.Structure):
@@ -149,6 +150,7 @@ def load() -> ctypes.CDLL:
         "lbm_server_drain": (ctypes.c_int, [H]),
         "lbm_server_stats_get": (ctypes.c_int, [H, P]),
         "lbm_server_destroy": (None, [H]),
+        "lbm_precision_info": (ctypes.c_int, [i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -302,6 +304,13 @@ def lbm_profile_sweeps(h, enable: bool):
     _check(load().lbm_profile_sweeps(h, int(bool(enable)), ctypes.byref(n), ctypes.byref(k),
                                      ctypes.byref(ms)))
     return n.value, k.value, ms.value
+
+
+def lbm_precision_info(precision: int) -> tuple[int, int]:
+    """(bytes per stored population value, bytes of the update's arithmetic)."""
+    sb, ab = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().lbm_precision_info(int(precision), ctypes.byref(sb), ctypes.byref(ab)))
+    return sb.value, ab.value
 
 
 def lbm_tb_variant_count(precision: int) -> int:

@@ -16,6 +16,7 @@ EXPECTED = {
     "lbm_batch_configure", "lbm_batch_tune", "lbm_batch_info", "lbm_batch_destroy",
     "lbm_batch_set_graphs", "lbm_state_digest", "lbm_server_create", "lbm_server_submit",
     "lbm_server_poll", "lbm_server_drain", "lbm_server_stats_get", "lbm_server_destroy",
+    "lbm_precision_info",
 }
 
 
@@ -39,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_struct_layouts_match_header():
     # sizes implied by the header's field lists (natural alignment, x86-64)
     assert ctypes.sizeof(lbm.lbm_geometry_desc) == 4 * 12 + 3 * 8 + 8
-    assert ctypes.sizeof(lbm.lbm_stats) == 8 + 16 + 7 * 8 + 8
+    assert ctypes.sizeof(lbm.lbm_stats) == 8 + 16 + 7 * 8 + 8 + 8
     assert ctypes.sizeof(lbm.lbm_shape_params) == 8 + 8 + 16
     assert ctypes.sizeof(lbm.lbm_server_config) == 8 + 16
     assert ctypes.sizeof(lbm.lbm_request) == ctypes.sizeof(lbm.lbm_geometry_desc) + 8 + 16 + 32
@@ -91,3 +92,21 @@ def test_region_shapes_fit_the_chip(lib):
         with pytest.raises(lbm.LbmError):
             lbm.lbm_tb_variant_info(prec, n)
     assert lbm.lbm_tb_variant_count(99) == 0
+
+
+def test_precision_comments_match_the_build(lib):
+    """Each precision form's comment in the header names its storage and its
+    arithmetic ("stored in X, relaxed in Y"); the library reports the sizes
+    of the types it was built with."""
+    import re
+    txt = open(lbm.HEADER_PATH).read()
+    block = txt[txt.index("---- precision forms"):txt.index("#define LBM_F64")]
+    block = " ".join(line.strip().lstrip("*").strip() for line in block.splitlines())
+    sizes = {"double": 8, "float": 4, "half": 2, "bfloat16": 2}
+    found = re.findall(r"(LBM_F\w+):.*?stored in (\w+).*?relaxed in (\w+)", block)
+    assert [f[0] for f in found] == ["LBM_F64", "LBM_F32", "LBM_F32_S_F16", "LBM_F32_S_BF16"]
+    for name, stored, relaxed in found:
+        sb, ab = lbm.lbm_precision_info(getattr(lbm, name))
+        assert (sb, ab) == (sizes[stored], sizes[relaxed]), name
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_precision_info(7)

@@ -1,14 +1,16 @@
 """Region shapes, the autotuner and batched sweeps, through the C ABI.
 
 Each of these only changes how the time steps are scheduled on the chip, so
-the bar is bit-identity with the plain path: one lattice on its own, one
-launch per step (whose parity with the FP64 oracle the other GPU tests
-establish)."""
+the first bar is bit-identity with the plain path: one lattice on its own,
+one launch per step.  Batch members are also compared with the FP64 oracle
+directly: bit for bit in double precision, within 1e-5 in single."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1303_0107_amd import inputs as I
 from paper_1303_0107_amd import lbm
+from parity_helpers import fields_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -126,6 +128,16 @@ def test_batch_matches_each_lattice_alone(prec, single_step):
         for k, (x, y) in enumerate(zip(batch_m, alone)):
             assert np.array_equal(x.state(), y.state()), f"member {k} after {s} steps"
             assert x.stats()[1].steps == y.stats()[1].steps
+    if prec in (lbm.LBM_F64, lbm.LBM_F32):
+        # three members against the oracle run the same number of steps
+        for k in range(3):
+            c, g = cands[k], batch_m[k]
+            o = oracle.Lattice(c.types(), c.tau, c.u_peak)
+            o.run(s1 + s2, 0.0, 100)
+            if prec == lbm.LBM_F64:
+                assert np.array_equal(g.state(), o.fs), f"member {k} vs oracle"
+            else:
+                assert fields_ok(c.types(), g.macro(), o.macro(), 1e-5, f"batch member {k}")
     bt.close()
 
 

@@ -13,6 +13,7 @@ import pytest
 import oracle
 from paper_1303_0107_amd import inputs as I
 from paper_1303_0107_amd import lbm
+from parity_helpers import EPS, _outlet_l1, field_errors, fields_ok, report, stats_ok
 
 pytestmark = pytest.mark.gpu
 
@@ -52,73 +53,6 @@ def _gpu():
 
 def _w():
     return oracle.velocity_set()[3]
-
-
-EPS = np.finfo(np.float64).eps
-
-
-def field_errors(types, g_field, o_field):
-    """(relative L2 error of u, of rho - 1) over non-solid cells, each divided
-    by its allowance for the given precision tolerance.  The oracle forms
-    rho = sum f_i with f_i = O(w_i), so its rho carries up to ~4 eps of
-    absolute rounding: relative to rho - 1 that is 4 eps |rho| / |rho - 1|,
-    added to the allowance (8 eps to cover both sides)."""
-    ns = types != 0
-    rg, xg, yg = (a[ns] for a in g_field)
-    ro, xo, yo = (a[ns] for a in o_field)
-    du = math.sqrt(((xg - xo) ** 2 + (yg - yo) ** 2).sum()) / \
-        max(math.sqrt((xo ** 2 + yo ** 2).sum()), 1e-300)
-    dnorm = max(np.linalg.norm(ro - 1.0), 1e-300)
-    dr = np.linalg.norm(rg - ro) / dnorm
-    floor = 8 * EPS * np.linalg.norm(ro) / dnorm
-    return du, dr, floor
-
-
-def fields_ok(types, g_field, o_field, tol, tag=""):
-    du, dr, floor = field_errors(types, g_field, o_field)
-    report(f"fields {tag}", du=du, drho=dr, drho_floor=floor)
-    return du < tol and dr < tol + floor
-
-
-def _outlet_l1(o):
-    """Per outlet: number of cells and the sum over its cells of |rho u_x|."""
-    t = o.types
-    rho, ux, _ = o.macro()
-    col = t[:, -1]
-    counts, l1, y = [], [], 0
-    while y < len(col):
-        if col[y] == 3:
-            y0 = y
-            while y < len(col) and col[y] == 3:
-                y += 1
-            counts.append(y - y0)
-            l1.append(float(np.abs(rho[y0:y, -1] * ux[y0:y, -1]).sum()))
-        else:
-            y += 1
-    return np.array(counts), np.array(l1), max(1.0, float(rho.max()))
-
-
-def stats_ok(g, o, tol, tag=""):
-    """Outlet fluxes and the pressure drop against the oracle.  A flux is a
-    sum over n cells of j_x = sum c_x f_i: its error is judged relative to the
-    sum of |rho u_x| over those cells (the flux's own condition), plus the
-    oracle's rounding floor of ~4 eps rho per cell; dp is a difference of
-    mean densities, floor 8 eps."""
-    fg, sg = g.stats()
-    so = o.outlet_stats()
-    counts, l1, rho_max = _outlet_l1(o)
-    allow_f = tol * l1 + 4 * EPS * counts * rho_max
-    ef = float(np.max(np.abs(fg - so.flow) / allow_f)) if len(so.flow) else 0.0
-    edp = abs(sg.dp - so.dp) / (tol * abs(so.dp) + 8 * EPS * rho_max)
-    report(f"stats {tag}", flux_over_allow=ef, dp_over_allow=edp,
-           flux_rel=float(np.max(np.abs(fg - so.flow) / np.abs(so.flow))) if len(so.flow) else 0.0,
-           dp_rel=abs(sg.dp - so.dp) / abs(so.dp) if so.dp else 0.0)
-    return ef < 1.0 and edp < 1.0, sg, so
-
-
-def report(tag, **kw):
-    print(tag, " ".join(f"{k}={v:.3e}" if isinstance(v, float) else f"{k}={v}"
-                        for k, v in kw.items()), flush=True)
 
 
 # ------------------------------------------------------------------ create
@@ -252,29 +186,38 @@ def test_half_storage_one_step(prec, amp, u, floor):
 def test_precision_study_2048x1024(prec, precision_oracle):
     """Precision study on the 2048x1024 four-level distributor (tau 0.55,
     u_peak 0.03), 20000 steps: each storage form against the double-precision
-    oracle on every outlet flux, the pressure drop, theta and D_g.  Float
-    storage meets 1e-5; the 16-bit forms are reported, and held only to
-    their storage resolution times the conditioning observed for float
-    storage (a regression guard, not a target)."""
+    oracle on every outlet flux (two-step means), the pressure drop, theta,
+    D_g and the whole fields.  Float storage meets 1e-5.  The 16-bit forms
+    miss it by their storage resolution; their errors are the stated table
+    below (measured on the MI355X), held to within a factor 2 either way."""
     o, so = precision_oracle
     wl = I.PRECISION_2048x1024
     t = wl.types()
     g = lbm.Lattice(t, wl.tau, wl.u_peak, precision=prec)
     g.run(20000, 0.0, 100)
     fg, sg = g.stats()
-    ef = float(np.max(np.abs(fg - so.flow) / np.abs(so.flow)))
-    edp = abs(sg.dp - so.dp) / abs(so.dp)
     du, dr, _ = field_errors(t, g.macro(), o.macro())
-    report(f"precision study prec={prec}", flux=ef, dp=edp, theta=abs(sg.theta - so.theta),
-           dg=abs(sg.dg - so.dg), du=du, drho=dr)
+    err = {"flux": float(np.max(np.abs(fg - so.flow) / np.abs(so.flow))),
+           "dp": abs(sg.dp - so.dp) / abs(so.dp), "theta": abs(sg.theta - so.theta),
+           "dg": abs(sg.dg - so.dg), "u": du, "rho": dr}
+    report(f"precision study prec={prec}", **err)
     assert np.array_equal(fg, fg[::-1])
     if prec == lbm.LBM_F32:
-        assert max(ef, edp, du, dr) < 1e-5
+        assert max(err.values()) < 1e-5
     else:
-        # float storage's error amplification on this run is < 1e-5 / 2^-24
-        # ~ 170; the 16-bit formats' half-ulp times that bounds theirs
-        half_ulp = 2.0 ** -11 if prec == lbm.LBM_F32_S_F16 else 2.0 ** -8
-        assert max(edp, du) < 170 * half_ulp
+        for k, v in STATED_16BIT[prec].items():
+            assert v / 2 <= err[k] <= 2 * v, (k, err[k], v)
+
+
+# Errors of the 16-bit storage forms against the oracle on the precision
+# study (2048x1024, 20000 steps): outlet fluxes and dp relative, theta and
+# D_g absolute, u and rho - 1 relative L2.
+STATED_16BIT = {
+    lbm.LBM_F32_S_F16: {"flux": 1.83e-3, "dp": 2.78e-4, "theta": 6.98e-4, "dg": 1.95e-4,
+                        "u": 1.65e-3, "rho": 5.98e-4},
+    lbm.LBM_F32_S_BF16: {"flux": 3.84e-2, "dp": 1.81e-2, "theta": 6.70e-3, "dg": 2.00e-3,
+                         "u": 3.12e-2, "rho": 2.54e-2},
+}
 
 
 # ------------------------------------------------------------------ windows
@@ -312,9 +255,14 @@ def test_f64_reproduces_the_oracle_bit_for_bit():
     for a, b in zip(g.macro(), o.macro()):
         assert np.array_equal(a, b)
     flow, sg = g.stats()
-    so = o.outlet_stats()
+    so = o.outlet_stats2()
     assert np.array_equal(flow, so.flow)
-    assert (sg.dp, sg.theta, sg.dg, sg.flow_in) == (so.dp, so.theta, so.dg, so.flow_in)
+    assert (sg.dp, sg.theta, sg.dg, sg.flow_in, sg.flow_p2) == \
+        (so.dp, so.theta, so.dg, so.flow_in, so.flow_p2)
+    # the mass is a block-wise sum on the device (a different summation order)
+    assert abs(sg.mass - so.mass) < 1e-13 * so.mass
+    # the statistics step leaves the state where it was
+    assert np.array_equal(g.state(), o.fs)
 
 
 @pytest.mark.parametrize("prec", [lbm.LBM_F32] + HALF)
@@ -367,7 +315,7 @@ def precision_oracle():
     wl = I.PRECISION_2048x1024
     o = oracle.Lattice(wl.types(), wl.tau, wl.u_peak)
     o.run(20000, 0.0, 100)
-    return o, o.outlet_stats()
+    return o, o.outlet_stats2()
 
 
 # ------------------------------------------------------------------ full size
@@ -389,25 +337,13 @@ def headline_oracle_steady():
     return o
 
 
-def f32_flux_allowance(o, tol):
-    """Single-precision storage rounds every stored offset d_i = f_i - w_i by
-    up to 2^-24 |d_i| each step.  At a steady state that rounding acts as a
-    persistent forcing; the slowest mode (the flux split between outlets)
-    integrates it over its e-folding time T_e.  Bound per outlet k with n_k
-    cells: T_e * 2^-24 * max|d| * n_k, plus tol times the flux."""
-    w = oracle.velocity_set()[3]
-    ns = o.types != 0
-    dmax = float(np.abs(o.fs[:, ns] - w[:, None]).max())
-    counts, l1, _ = _outlet_l1(o)
-    return tol * l1 + o.t_efold * 2.0 ** -24 * dmax * counts
-
-
 @pytest.mark.parametrize("prec", PRECS)
 def test_headline_lattice_full_size_steady(prec, headline_oracle_steady):
     """The 1024x512 distributor in the launch configuration the benchmark
     times, run to its steady flow field (the field the method consumes,
-    Sec. 2.3 step 2) on both sides: whole fields, every outlet flux and the
-    pressure drop compared."""
+    Sec. 2.3 step 2) on both sides: whole fields, every outlet flux (the
+    steady flow rates, means over two consecutive steps) and the pressure
+    drop compared at the precision's tolerance."""
     o = headline_oracle_steady
     wl = I.HEADLINE_1024x512
     t = wl.types()
@@ -415,40 +351,52 @@ def test_headline_lattice_full_size_steady(prec, headline_oracle_steady):
     rc, steps, r = g.run(STEADY_STEPS, 0.0, 100)
     report(f"gpu 1024x512 steady prec={prec}", steps=steps, residual=r, oracle_residual=o.residual)
     tol = TOL[prec]
-    gf = g.macro()
-    ok_f = fields_ok(t, gf, o.macro(), tol, f"1024x512 steady prec={prec}")
+    ok_f = fields_ok(t, g.macro(), o.macro(), tol, f"1024x512 steady prec={prec}")
     ok_s, sg, so = stats_ok(g, o, tol, f"1024x512 steady prec={prec}")
+    report("period-two flux component", gpu=sg.flow_p2, oracle=so.flow_p2,
+           rel=so.flow_p2 / float(np.abs(so.flow).max()))
     if prec == lbm.LBM_F64:
         assert np.array_equal(g.state(), o.fs), "double path must match the oracle bitwise"
-        assert ok_f and ok_s
-    else:
-        # u, rho - 1 and the pressure drop meet 1e-5; the per-outlet fluxes
-        # are held to the storage-rounding bound of f32_flux_allowance
-        assert ok_f
-        assert abs(sg.dp - so.dp) < tol * abs(so.dp)
-        fg, _ = g.stats()
-        allow = f32_flux_allowance(o, tol)
-        rel = np.abs(fg - so.flow) / np.abs(so.flow)
-        report("f32 flux", max_rel=float(rel.max()),
-               over_allow=float(np.max(np.abs(fg - so.flow) / allow)))
-        assert np.all(np.abs(fg - so.flow) < allow)
+        assert sg.flow_p2 == so.flow_p2
+    assert ok_f and ok_s
+    assert abs(sg.theta - so.theta) < tol and abs(sg.dg - so.dg) < 10 * tol
 
 
-def test_largest_lattice_sampled_f32():
-    """4096x2048 all-fluid channel (the largest lattice in the workloads),
-    FP32: 50 steps, compared on every 7th row."""
-    nx, ny = 4096, 2048
-    t = I.channel(nx, ny)
-    g = lbm.Lattice(t, 0.6, 0.04, precision=lbm.LBM_F32)
+LARGEST_STEPS = 3000
+
+
+@pytest.fixture(scope="module")
+def largest_oracle():
+    """A 4096x2048 four-level distributor (the largest lattice the serving
+    workload draws) advanced 3000 steps from rest by the oracle: the start-up
+    pressure wave (speed c_s ~ 0.58 cells per step) has crossed some 1700
+    columns and the inlet jet has entered the first channel."""
+    t = I.distributor(4096, 2048, 4, I.default_widths(2048, 4))
     o = oracle.Lattice(t, 0.6, 0.04)
-    g.run(50, 0.0, 50)
-    o.run(50, 0.0, 50)
-    gr, gx, gy = g.macro()
-    orr, ox, oy = o.macro()
-    rows = slice(1, ny - 1, 7)
-    sub = t[rows]
-    assert fields_ok(sub, (gr[rows], gx[rows], gy[rows]), (orr[rows], ox[rows], oy[rows]),
-                     1e-5, "4096x2048 f32 sampled")
+    o.run(LARGEST_STEPS, 0.0, 100)
+    return o, o.outlet_stats2()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", PRECS)
+def test_largest_lattice_developed_flow(prec, largest_oracle):
+    """4096x2048 through the benchmark's launch path (temporal blocking):
+    double precision bit for bit with the oracle, single precision within
+    1e-5 on the whole fields, the pressure drop and the inflow."""
+    o, so = largest_oracle
+    t = o.types
+    g = lbm.Lattice(t, 0.6, 0.04, precision=prec)
+    rc, steps, _ = g.run(LARGEST_STEPS, 0.0, 100)
+    assert rc == 0 and steps == LARGEST_STEPS
+    if prec == lbm.LBM_F64:
+        assert np.array_equal(g.state(), o.fs)
+    else:
+        assert fields_ok(t, g.macro(), o.macro(), 1e-5, "4096x2048 f32")
+    flow, sg = g.stats()
+    tol = TOL[prec]
+    assert abs(sg.dp - so.dp) < tol * abs(so.dp)
+    assert abs(sg.flow_in - so.flow_in) < tol * abs(so.flow_in)
+    report("4096x2048", prec=prec, dp=sg.dp, flow_in=sg.flow_in)
 
 
 # ------------------------------------------------------------------ exchange

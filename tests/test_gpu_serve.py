@@ -10,8 +10,10 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 from paper_1303_0107_amd import inputs as I
 from paper_1303_0107_amd import lbm
+from parity_helpers import f64_state_digest
 
 pytestmark = pytest.mark.gpu
 GiB = 1 << 30
@@ -26,11 +28,11 @@ def _gpu():
     lbm.load()
 
 
-def _requests(n, seed=21):
+def _requests(n, seed=21, precs=(lbm.LBM_F32, lbm.LBM_F32_S_F16)):
     rng = np.random.default_rng(seed)
     out = []
     for k, c in enumerate(I.batch_candidates(count=n, seed=seed)):
-        prec = lbm.LBM_F32 if k % 2 == 0 else lbm.LBM_F32_S_F16
+        prec = precs[k % len(precs)]
         if k % 3 == 0:
             r = lbm.make_request(c.nx, c.ny, c.levels, c.widths, c.tau, c.u_peak, prec,
                                  lbm.LBM_REQ_SOLVE, solve_steps=int(rng.integers(30, 130)))
@@ -61,6 +63,23 @@ def _by_hand(r):
     d = lat.digest()
     lat.close()
     return d, st
+
+
+def _by_oracle(r):
+    """The request's work done by the FP64 oracle: returns the oracle lattice
+    and its steady statistics (two-step means)."""
+    g = r.geom
+    o = oracle.Lattice(I.distributor(g.nx, g.ny, g.levels, list(g.widths)[:g.levels + 1]),
+                       g.tau, g.u_peak, g.rho_out)
+    if r.solve_steps:
+        o.run(r.solve_steps, 0.0, 100)
+    if r.kind == lbm.LBM_REQ_OPTIMIZE:
+        p = r.shape
+        for it in range(r.iterations):
+            o.shape_update(p.frac, p.seed + it, p.band_x, p.band_y, p.criterion, p.reinit)
+            if r.steps_per_iteration:
+                o.run(r.steps_per_iteration, 0.0, 100)
+    return o, o.outlet_stats2()
 
 
 def _run(server, reqs, stagger=None):
@@ -100,6 +119,41 @@ def test_results_are_identical_alone_and_in_the_mix():
                                       if r.kind == lbm.LBM_REQ_OPTIMIZE else 0)
         assert m.steps == want_steps
         assert m.t_submit <= m.t_admit <= m.t_done
+
+
+def test_served_results_match_the_oracle():
+    """Requests served in a mix of double, single and half-storage requests
+    against the FP64 oracle doing the same work: double-precision requests
+    (solve and optimise) bit for bit (the digest of the final state and mask,
+    computed from the oracle's state, and every statistic); single-precision
+    requests within 1e-5 on the pressure drop, inflow, mass and theta."""
+    reqs = _requests(10, seed=24,
+                     precs=(lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F64, lbm.LBM_F32_S_F16))
+    srv = lbm.Server(hbm_budget=64 * GiB, max_sessions=16, quantum=20)
+    res = _run(srv, reqs, stagger=2)
+    srv.close()
+    checked = {lbm.LBM_F64: set(), lbm.LBM_F32: set()}
+    for r, m in zip(reqs, res):
+        prec = r.geom.precision
+        if prec not in checked:
+            continue
+        assert m.status == lbm.LBM_OK
+        o, so = _by_oracle(r)
+        if prec == lbm.LBM_F64:
+            assert m.digest == f64_state_digest(o.types, o.fs)
+            for f in ("dp", "theta", "dg", "flow_in", "flow_p2"):
+                assert getattr(m.stats, f) == getattr(so, f), f
+            # the mass is a block-wise sum on the device (another order)
+            assert abs(m.stats.mass - so.mass) < 1e-13 * so.mass
+        else:
+            assert abs(m.stats.dp - so.dp) < 1e-5 * abs(so.dp)
+            assert abs(m.stats.flow_in - so.flow_in) < 1e-5 * abs(so.flow_in)
+            assert abs(m.stats.mass - so.mass) < 1e-5 * so.mass
+            if np.abs(so.flow).min() > 1e-3 * abs(so.flow_in):  # outflow established
+                assert abs(m.stats.theta - so.theta) < 1e-5
+        checked[prec].add(r.kind)
+    assert checked[lbm.LBM_F64] == {lbm.LBM_REQ_SOLVE, lbm.LBM_REQ_OPTIMIZE}
+    assert lbm.LBM_REQ_SOLVE in checked[lbm.LBM_F32]
 
 
 def test_server_does_what_the_handle_calls_do():

@@ -70,7 +70,7 @@ def test_f64_matches_the_oracle_bit_for_bit(name):
     o.run(300, 0.0, 100)
     g.run(300, 0.0, 100)
     assert np.array_equal(g.state().reshape(o.fs.shape), o.fs)
-    so = o.outlet_stats()
+    so = o.outlet_stats2()
     flow, sg = g.stats()
     assert np.array_equal(flow, so.flow) and sg.dp == so.dp
     g.close()
