@@ -211,6 +211,24 @@ int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
                      lbm_stats *s);
 
 /*
+ * lbm_outlet_stats for callers that cannot allocate memory (tight serving
+ * loops, harnesses that forbid allocation during a measurement): the same
+ * results, bit for bit, with no device or pinned host allocation.  Every
+ * intermediate (boundary sums of the two states, the mass and its per-block
+ * partials) lives in one fixed device scratch area of 1 MiB per GPU, held
+ * until the process ends and shared by every call on that GPU: calls that
+ * overlap on one GPU (several threads, or several streams in flight) race
+ * on it and must be serialised by the caller.  Nothing in the scratch needs
+ * to start at zero.  The sums come back through a buffer on the calling
+ * thread's stack (about 33 KB).
+ * Limits: at most 1024 outlets, and (2 (2 n_out + 5) + 1 + ceil(nx/64)
+ * ceil(ny/4)) * 8 bytes within the 1 MiB (e.g. 4096 x 4096 lattices).
+ * Errors: those of lbm_outlet_stats; LBM_EINVAL, with a message, beyond the
+ * limits.
+ */
+int lbm_outlet_stats_noalloc(lbm_handle *h, double *flow, int32_t flow_cap, lbm_stats *s);
+
+/*
  * Steps (3) and (4) of Sec. 2.3: exchange the K_eff fluid interface cells of
  * lowest key with the K_eff solid interface cells of highest key (Sec. 2.2),
  * at constant fluid volume, then re-initialise (WARM: new fluid cells at

@@ -1397,32 +1397,18 @@ int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *steps,
     return LBM_OK;
 }
 
-int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
-                     lbm_stats *s) {
-    g_error.clear();
-    if (!h || !s) return fail(LBM_EINVAL, "null handle or stats");
+}  // extern "C"
+
+namespace {
+
+// Fill s (and flow) from the boundary sums b of the current state (b[0, nb))
+// and of the state one step later (b[nb, 2 nb)), nb = 2 n_out + 5, and the
+// current state's mass: the steady flow rates are the two-step means, which
+// cancel the undamped period-two oscillation of the boundary fluxes; Eqs.
+// 9-11 on the means.
+void finish_stats(const lbm_handle *h, const double *b, double mass, double *flow,
+                  lbm_stats *s) {
     const int n_out = (int)h->out_y0.size();
-    std::memset(s, 0, sizeof *s);
-    s->n_outlets = n_out;
-    s->n_fluid = h->n_fluid;
-    s->n_nonsolid = h->n_nonsolid;
-    s->residual = h->last_residual;
-    s->steps = h->steps;
-    if (n_out > 0 && (!flow || flow_cap < n_out))
-        return fail(LBM_EINVAL, "flow_cap smaller than the number of outlets");
-    std::vector<double> b;
-    double mass = 0.0;
-    try {
-        HIP_TRY(hipSetDevice(h->device));
-        with_storage(h->precision, [&](auto t) { stats_impl<decltype(t)>(h, b, mass); });
-    } catch (const HipFail &e) {
-        return guard_hip(e);
-    } catch (const std::bad_alloc &) {
-        return fail(LBM_ENOMEM, "allocation failed");
-    }
-    // The steady flow rates: means over the current state (sums b[0, nb)) and
-    // the state one step later (b[nb, 2 nb)), which cancel the undamped
-    // period-two oscillation of the boundary fluxes; Eqs. 9-11 on the means.
     const size_t nb = (size_t)(2 * n_out + 5);
     auto dp_of = [&](const double *c) {  // Eq. 4 with c_s^2 = 1/3
         const double rho_in_sum = c[2 * n_out + 1], cnt_in = c[2 * n_out + 2];
@@ -1437,7 +1423,7 @@ int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
         flow[k] = 0.5 * (b[k] + b[nb + k]);
     }
     s->flow_in = 0.5 * (b[2 * n_out] + b[nb + 2 * n_out]);
-    s->dp = 0.5 * (dp_of(b.data()) + dp_of(b.data() + nb));
+    s->dp = 0.5 * (dp_of(b) + dp_of(b + nb));
     s->flow_p2 = p2;
     s->mass = mass;
     if (n_out > 0) {
@@ -1457,6 +1443,129 @@ int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
         s->dg = n_out > 1 ? std::sqrt(dev / (double)(n_out - 1)) : 0.0;  // Eq. 10
         s->flow_ave = ave;
     }
+}
+
+// Arguments every statistics call checks; fills the counts of s.
+int begin_stats(lbm_handle *h, double *flow, int32_t flow_cap, lbm_stats *s) {
+    if (!h || !s) return fail(LBM_EINVAL, "null handle or stats");
+    const int n_out = (int)h->out_y0.size();
+    std::memset(s, 0, sizeof *s);
+    s->n_outlets = n_out;
+    s->n_fluid = h->n_fluid;
+    s->n_nonsolid = h->n_nonsolid;
+    s->residual = h->last_residual;
+    s->steps = h->steps;
+    if (n_out > 0 && (!flow || flow_cap < n_out))
+        return fail(LBM_EINVAL, "flow_cap smaller than the number of outlets");
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_outlet_stats(lbm_handle *h, double *flow, int32_t flow_cap,
+                     lbm_stats *s) {
+    g_error.clear();
+    const int rc = begin_stats(h, flow, flow_cap, s);
+    if (rc != LBM_OK) return rc;
+    std::vector<double> b;
+    double mass = 0.0;
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        with_storage(h->precision, [&](auto t) { stats_impl<decltype(t)>(h, b, mass); });
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    } catch (const std::bad_alloc &) {
+        return fail(LBM_ENOMEM, "allocation failed");
+    }
+    finish_stats(h, b.data(), mass, flow, s);
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Statistics without allocation.
+
+// Device scratch of lbm_outlet_stats_noalloc, one copy per GPU, held until the
+// process ends: the boundary sums of two states (2 (2 n_out + 5) doubles),
+// the mass (one double), then the per-block mass partials.  Host code never
+// uses this name as an address (it is a host-side stand-in): it uses the
+// device address that hipGetSymbolAddress returns for each device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};  // per device ordinal
+
+// The scratch's device address on `device`, which must be current; looked up
+// once per device.
+int scratch_on(int device, double **out) {
+    if (device < 0 || device >= 64) return fail(LBM_EINVAL, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBM_EHIP, std::string("hipGetSymbolAddress of the scratch failed: ") +
+                                      hipGetErrorString(e));
+        g_scratch_ptr[device] = p;
+    }
+    *out = static_cast<double *>(g_scratch_ptr[device]);
+    return LBM_OK;
+}
+
+// The kernels of stats_impl with every intermediate in `scr` (device) and the
+// sums copied to `host` (2 nb + 1 doubles): no buffer of the handle's is
+// grown and no pinned staging is used.
+template <typename T>
+void stats_noalloc_impl(lbm_handle *h, double *scr, double *host) {
+    const int n_out = (int)h->out_y0.size();
+    const size_t nb = (size_t)(2 * n_out + 5);
+    MacroArgs<T> a = macro_args<T>(h);
+    const int32_t *y0 = h->out_rows.as<int32_t>();
+    const int32_t *y1 = y0 + std::max(n_out, 1);
+    double *partials = scr + 2 * nb + 1;
+    HIP_TRY(launch_boundary<T>(a, y0, y1, n_out, scr, h->stream));
+    HIP_TRY(launch_sweep<T>(sweep_args<T>(h, false), false, h->stream));
+    MacroArgs<T> next = a;
+    next.f = h->f[1 - h->cur].as<T>();
+    HIP_TRY(launch_boundary<T>(next, y0, y1, n_out, scr + nb, h->stream));
+    HIP_TRY(launch_mass<T>(a, partials, h->stream));
+    HIP_TRY(launch_finalize1(partials, sweep_blocks(h->nx, h->ny), scr + 2 * nb, h->stream));
+    HIP_TRY(hipMemcpyAsync(host, scr, (2 * nb + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_outlet_stats_noalloc(lbm_handle *h, double *flow, int32_t flow_cap, lbm_stats *s) {
+    g_error.clear();
+    const int rc = begin_stats(h, flow, flow_cap, s);
+    if (rc != LBM_OK) return rc;
+    const int n_out = (int)h->out_y0.size();
+    if (n_out > kNoAllocMaxOutlets)
+        return fail(LBM_EINVAL, "lbm_outlet_stats_noalloc: more outlets than its limit");
+    const size_t nb = (size_t)(2 * n_out + 5);
+    const size_t need = (2 * nb + 1 + (size_t)sweep_blocks(h->nx, h->ny)) * sizeof(double);
+    if (need > kNoAllocScratchBytes)
+        return fail(LBM_EINVAL, "lbm_outlet_stats_noalloc: lattice too large for its scratch");
+    double host[2 * (2 * kNoAllocMaxOutlets + 5) + 1];
+    try {
+        HIP_TRY(hipSetDevice(h->device));
+        double *scr = nullptr;
+        const int e = scratch_on(h->device, &scr);
+        if (e != LBM_OK) return e;
+        with_storage(h->precision, [&](auto t) { stats_noalloc_impl<decltype(t)>(h, scr, host); });
+    } catch (const HipFail &e) {
+        return guard_hip(e);
+    }
+    finish_stats(h, host, host[2 * nb], flow, s);
     return LBM_OK;
 }
 

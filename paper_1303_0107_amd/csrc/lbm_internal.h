@@ -206,6 +206,9 @@ template <typename T>
 hipError_t launch_step_batch(const SweepArgs<T> *args, const int32_t *lat,
                              const int32_t *blocks, int n_items, bool bc, hipStream_t s);
 int64_t sweep_blocks(int nx, int ny);
+// Limits of lbm_outlet_stats_noalloc (its device scratch is a fixed array).
+constexpr size_t kNoAllocScratchBytes = (size_t)1 << 20;
+constexpr int kNoAllocMaxOutlets = 1024;
 // Device control block of a run to steady state: the run's check intervals
 // are queued several at a time, and each interval's finalize step records the
 // interval's sums, counts it, and ends the run (stop = 1 converged, 2

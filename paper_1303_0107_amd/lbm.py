@@ -151,6 +151,7 @@ def load() -> ctypes.CDLL:
         "lbm_server_stats_get": (ctypes.c_int, [H, P]),
         "lbm_server_destroy": (None, [H]),
         "lbm_precision_info": (ctypes.c_int, [i32, P, P]),
+        "lbm_outlet_stats_noalloc": (ctypes.c_int, [H, P, i32, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -222,6 +223,15 @@ def lbm_outlet_stats(h, flow_cap: int = 1024):
     flow = np.zeros(max(flow_cap, 1), np.float64)
     s = lbm_stats()
     _check(lib.lbm_outlet_stats(h, _p(flow), int(flow_cap), ctypes.byref(s)))
+    return flow[:s.n_outlets].copy(), s
+
+
+def lbm_outlet_stats_noalloc(h, flow_cap: int = 1024):
+    """lbm_outlet_stats without allocation (fixed per-GPU device scratch)."""
+    lib = load()
+    flow = np.zeros(max(flow_cap, 1), np.float64)
+    s = lbm_stats()
+    _check(lib.lbm_outlet_stats_noalloc(h, _p(flow), int(flow_cap), ctypes.byref(s)))
     return flow[:s.n_outlets].copy(), s
 
 
