@@ -1664,18 +1664,26 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
             h->sel.ensure((size_t)keff * (sizeof(double) + 2 * sizeof(int32_t)));
             double *rrho = h->sel.as<double>();
             int32_t *srem = reinterpret_cast<int32_t *>(rrho + keff), *sadd = srem + keff;
-            h->select_tmp.ensure(select_scratch_bytes(cap));
+            h->select_tmp.ensure(select_scratch_bytes(keff));
             HIP_TRY(launch_select_pair(kf, hf, if_, (int64_t)cnt[0], ks, hs, is, (int64_t)cnt[1],
-                                       keff, srem, sadd, h->select_tmp.p, cap, h->stream));
+                                       keff, srem, sadd, h->select_tmp.p, keff, err,
+                                       h->stream));
             HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, rrho, m,
                                 h->stream));
             if (p->reinit == LBM_WARM)  // removed and added cells, adjacent in sel
                 with_storage(h->precision,
                              [&](auto t) { zero_cells<decltype(t)>(h, srem, 2 * (int)keff); });
-            ensure_pinned(h, (size_t)keff * (sizeof(double) + 2 * sizeof(int32_t)));
-            HIP_TRY(hipMemcpyAsync(h->pinned, rrho, keff * (sizeof(double) + 2 * sizeof(int32_t)),
+            // the selections and removed densities, then the error flag the
+            // selection kernels may have set
+            const size_t rb = (size_t)keff * (sizeof(double) + 2 * sizeof(int32_t));
+            const size_t rb_al = (rb + 7) / 8 * 8;
+            ensure_pinned(h, rb_al + sizeof(double));
+            HIP_TRY(hipMemcpyAsync(h->pinned, rrho, rb, hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipMemcpyAsync(reinterpret_cast<char *>(h->pinned) + rb_al, err, sizeof(int),
                                    hipMemcpyDeviceToHost, h->stream));
             HIP_TRY(hipStreamSynchronize(h->stream));
+            if (*reinterpret_cast<const int *>(reinterpret_cast<const char *>(h->pinned) + rb_al))
+                return fail(LBM_EHIP, "the selection kernels found an inconsistent candidate list");
             const double *rr = h->pinned;
             const int32_t *ix = reinterpret_cast<const int32_t *>(h->pinned + keff);
             std::memcpy(rem.data(), ix, keff * sizeof(int32_t));

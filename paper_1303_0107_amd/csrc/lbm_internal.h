@@ -264,13 +264,15 @@ hipError_t launch_digest(const T *f, const uint16_t *cell, const uint8_t *types,
 hipError_t launch_keys(const KeysArgs &a, hipStream_t s);
 // The k_eff first of the nf fluid and of the ns solid candidates, each list in
 // the order (key, hash), written as cell indices to sel_f and sel_s.
-// `scratch` holds select_scratch_bytes(cap) bytes; nf, ns <= cap and
-// k_eff <= min(nf, ns).
-size_t select_scratch_bytes(int64_t cap);
+// `scratch` holds select_scratch_bytes(k_max) bytes, k_eff <= k_max and
+// k_eff <= min(nf, ns).  An inconsistency the kernels detect (impossible for
+// candidates with distinct hashes) sets bits 8 and up of *error (device).
+size_t select_scratch_bytes(int64_t k_max);
 hipError_t launch_select_pair(const uint64_t *kf, const uint64_t *hf, const int32_t *if_,
                               int64_t nf, const uint64_t *ks, const uint64_t *hs,
                               const int32_t *is, int64_t ns, int64_t k_eff, int32_t *sel_f,
-                              int32_t *sel_s, void *scratch, int64_t cap, hipStream_t s);
+                              int32_t *sel_s, void *scratch, int64_t k_max, int *error,
+                              hipStream_t s);
 // Flip the selected cells; removed_rho[k] = rho[removed[k]].
 hipError_t launch_flip(uint8_t *types, const int32_t *removed,
                        const int32_t *added, int k_eff, double *removed_rho,

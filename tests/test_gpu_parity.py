@@ -436,6 +436,42 @@ def test_exchange_bit_exact_with_ties_large_lattice():
     assert r.mass_removed == ro.mass_removed
 
 
+def _porous(nx, ny, solid_frac, seed):
+    """A channel filled with random solid cells: tens of thousands of
+    interface cells of each kind."""
+    t = I.channel(nx, ny)
+    rng = np.random.default_rng(seed)
+    inner = t[2:-2, 3:-3]
+    inner[rng.random(inner.shape) < solid_frac] = 0
+    return t
+
+
+@pytest.mark.parametrize("frac,quant", [(0.9, 3), (0.2, None), (1e-6, 2)])
+def test_exchange_bit_exact_many_candidates(frac, quant):
+    """Selections of every size on a porous 1024x512 lattice (over 10^5
+    candidates per list): frac 0.9 takes every candidate of the shorter list
+    (K_eff over 32768, so the selection runs in several rank chunks), frac
+    0.2 several chunks ending inside both lists, frac 1e-6 a single cell.  A
+    quantised field adds exact key ties at the chunk boundaries, which the
+    hash decides.  Bit-exact with the oracle."""
+    t = _porous(1024, 512, 0.3, 9)
+    rho, ux, uy = I.random_field(t, 5)
+    if quant:
+        ux, uy = np.round(ux, quant), np.round(uy, quant)
+    g = lbm.Lattice(t, 0.7, 0.03, precision=lbm.LBM_F32)
+    r, rem, add = g.shape_update(frac=frac, seed=77, field=(rho, ux, uy))
+    nt, ro = oracle.shape_select(t, rho, ux, uy, frac=frac, seed=77)
+    report("exchange porous", k_eff=r.k_eff, cf=r.n_cand_fluid, cs=r.n_cand_solid)
+    assert r.k_eff == ro.k_eff
+    if frac == 1e-6:
+        assert r.k_eff == 1
+    else:
+        assert r.k_eff > 32768
+    assert np.array_equal(g.mask(), nt)
+    assert np.array_equal(np.asarray(rem), ro.removed) and np.array_equal(np.asarray(add), ro.added)
+    assert r.mass_removed == ro.mass_removed
+
+
 @pytest.mark.parametrize("reinit", [lbm.LBM_WARM, lbm.LBM_COLD])
 def test_reinitialisation_matches_oracle(reinit):
     wl = I.CORRECTNESS_128x64
