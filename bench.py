@@ -7,7 +7,8 @@ step cap) -> outlet reductions (Eq. 4, Eqs. 9-11).  Before the warm-up the
 lattice is brought from rest to steady state (untimed).
 
 value  = lattice updates per second over the timed steps (all nx*ny cells,
-         MLUPS), whole-job wall time between two device synchronisations.
+         MLUPS), whole-job wall time between two device synchronisations;
+         mflups counts the non-solid cells only.
 roofline: the sweep kernel.  Algorithmic bytes per time step
          = 18 * s * N_nonsolid + N  (each non-solid population read and
          written once, s bytes each, plus one cell byte per cell); a launch
@@ -15,7 +16,18 @@ roofline: the sweep kernel.  Algorithmic bytes per time step
          the per-step figure.  Divided by the mean launch time of the sweeps
          inside the timed region, measured with HIP events recorded on the
          handle's stream around each residual-check interval's launches.
-cpu_baseline: the FP64 oracle on the same lattice, a bounded number of steps.
+         With temporal blocking a launch moves far fewer bytes than that
+         (the populations cross HBM once per launch, not once per step), so
+         this is an effective bandwidth; the measured HBM bytes per launch
+         (rocprofv3 counters) over the same launch time are reported beside
+         it, and so is the kernel's actual limiter, the vector ALU issue rate
+         (measured VALU instructions per launch over the launch time, against
+         the chip's non-packed rate).
+Default legs (--legs): the headline optimisation loop; the all-fluid
+1024x512 channel (sweeps only: the workload the HBM-roofline target is set
+on); a short serving run (Poisson arrivals, p50/p99 latency).
+cpu_baseline: the FP64 oracle on the same lattice, a bounded number of steps,
+on every host thread and on one.
 """
 from __future__ import annotations
 
@@ -111,10 +123,21 @@ def copy_ceiling(nbytes: int = 1 << 28):
     return best
 
 
-def cpu_baseline(types, w, seconds: float):
-    """The oracle from rest on the same lattice, in chunks of 100 steps
-    (residual check each) until `seconds` of wall time have passed."""
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(types, w, seconds: float, threads: int | None):
     import oracle
+    if threads:
+        oracle.set_num_threads(threads)
     lat = oracle.Lattice(types, w.tau, w.u_peak)
     steps = 0
     t0 = time.perf_counter()
@@ -124,10 +147,27 @@ def cpu_baseline(types, w, seconds: float):
         dt = time.perf_counter() - t0
         if dt >= seconds:
             break
-    return {"value": types.size * steps / dt / 1e6, "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
+    return types.size * steps / dt / 1e6, steps, dt, oracle.num_threads()
+
+
+def cpu_baseline(types, w, seconds: float):
+    """The oracle from rest on the same lattice, in chunks of 100 steps
+    (residual check each) until `seconds` of wall time have passed: once on
+    every host thread, once on a single thread."""
+    import oracle
+    # the host threads this process may use (the job's share of the host)
+    all_threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    mlups, steps, dt, cores = _oracle_rate(types, w, seconds, all_threads)
+    one, steps1, dt1, _ = _oracle_rate(types, w, seconds / 2, 1)
+    oracle.set_num_threads(all_threads)
+    nns = int((types != 0).sum())
+    return {"value": mlups, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{steps} FP64 time steps of the {w.name} lattice from rest "
-                      f"({dt:.1f} s), residual checks every 100 steps"}
+                      f"({dt:.1f} s), residual checks every 100 steps",
+            "mflups": mlups * nns / types.size,
+            "single_thread": {"value": one, "unit": "MLUPS", "cores": 1,
+                              "sample": f"{steps1} time steps ({dt1:.1f} s)"},
+            "cpu_model": cpu_model(), "host_threads": all_threads}
 
 
 BATCH_WORKLOAD = "batch-256-candidates"
@@ -247,7 +287,7 @@ def bench_batch(args) -> int:
 SERVE_WORKLOAD = "serve-poisson-50rps"
 
 
-def bench_serve(args) -> int:
+def serve_leg(args, rate: float, seconds: float):
     """Serving: Poisson arrivals of solve / optimise requests (FP32 and FP16
     offset storage) submitted in real time to the request server (continuous
     batching, admission by HBM footprint).  value = aggregate lattice updates
@@ -256,17 +296,17 @@ def bench_serve(args) -> int:
     minus submission per request, p50 / p99.  roofline: whole rounds (batched
     sweeps plus the host work of events), algorithmic bytes of the steps
     taken over the time spent in rounds -- a lower bound on the kernels'
-    rate, not a kernel measurement."""
+    rate, not a kernel measurement.  Returns (result dict, failures)."""
     import numpy as np
     import torch
 
     from paper_1303_0107_amd import inputs as I
     from paper_1303_0107_amd import lbm
 
-    reqs = I.serving_requests(rate=args.serve_rate, seconds=args.serve_seconds, seed=5)
+    reqs = I.serving_requests(rate=rate, seconds=seconds, seed=5)
     prec = {"f32": lbm.LBM_F32, "f16": lbm.LBM_F32_S_F16}
     s_bytes = {"f32": 4, "f16": 2}
-    print(f"# {SERVE_WORKLOAD}: {len(reqs)} requests over {args.serve_seconds} s",
+    print(f"# serving: {len(reqs)} requests over {seconds} s at {rate}/s",
           file=sys.stderr, flush=True)
     crs = []
     nns = []
@@ -330,7 +370,7 @@ def bench_serve(args) -> int:
         "data": "synthetic",
         "config": {
             "workload": SERVE_WORKLOAD, "requests": len(reqs),
-            "arrivals": f"Poisson {args.serve_rate}/s for {args.serve_seconds} s, seed 5",
+            "arrivals": f"Poisson {rate}/s for {seconds} s, seed 5",
             "lattices": "nx = 64 round(256 2^U(0,4) / 64), ny = nx/2; generator as the "
                         "batched candidates",
             "mix": "FP32 / FP16 offset storage 50/50 (float arithmetic); solve 500 steps / "
@@ -356,6 +396,14 @@ def bench_serve(args) -> int:
             "kernel": "server rounds (batched sweeps + event host work), not a single kernel",
         },
     }
+    return out, len(bad)
+
+
+def bench_serve(args) -> int:
+    """The serving workload on its own (value = its aggregate MLUPS)."""
+    from paper_1303_0107_amd import inputs as I
+    out, bad = serve_leg(args, args.serve_rate, args.serve_seconds)
+    out["latency_ms"] = out["config"]["latency_ms"]
     if not args.no_cpu:
         w = I.HEADLINE_1024x512
         out["cpu_baseline"] = cpu_baseline(w.types(), w, args.cpu_seconds)
@@ -363,65 +411,56 @@ def bench_serve(args) -> int:
     return 0 if not bad else 1
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed optimisation iterations")
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["f32", "f64", "f16", "bf16"], default="f32",
-                    help="population storage (f64: double storage and arithmetic; f32: float "
-                         "storage, float arithmetic; f16/bf16: 16-bit storage, float arithmetic)")
-    ap.add_argument("--workload", default="distributor-1024x512-L3")
-    ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--cap", type=int, default=200000, help="step cap per solve")
-    ap.add_argument("--settle-cap", type=int, default=None,
-                    help="step cap of the untimed solve from rest (default: workload's)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batch-steps", type=int, default=10000,
-                    help="time steps per benchmark step of the batched workload")
-    ap.add_argument("--batch-count", type=int, default=256)
-    ap.add_argument("--tune-steps", type=int, default=256,
-                    help="steps per autotuner trial (batched workload)")
-    ap.add_argument("--serve-rate", type=float, default=50.0)
-    ap.add_argument("--serve-seconds", type=float, default=60.0)
-    ap.add_argument("--hbm-budget-gb", type=float, default=32.0)
-    ap.add_argument("--max-sessions", type=int, default=64)
-    ap.add_argument("--quantum", type=int, default=20)
-    args = ap.parse_args()
+# Vector ALU instructions (wave instructions, rocprofv3 SQ_INSTS_VALU) of one
+# full launch of the blocked sweep, keyed like the traffic table;
+# profiles/sweep_tb_*_counters.txt.  Each wave instruction occupies a SIMD
+# for 4 cycles (64 lanes on 16-wide SIMDs; packed FP32 is not used), so the
+# chip issues at most 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave
+# instructions per second.
+MEASURED_VALU_PER_FULL_LAUNCH = {}
+VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: the library has no multi-GPU path",
-              file=sys.stderr)
-        return 2
 
+def hbm_and_limiter(roof: dict, traffic, valu, avg_ms: float) -> None:
+    """Add the measured HBM rate and the ALU-issue bound to a roofline dict."""
+    roof["effective"] = "algorithmic bytes of every step a launch advances over the launch " \
+                        "time (with temporal blocking, above what HBM carries)"
+    if traffic:
+        gbs = traffic / (avg_ms * 1e-3) / 1e9
+        roof["hbm_measured_GBs"] = round(gbs, 1)
+        roof["hbm_measured_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    else:
+        roof["hbm_measured_GBs"] = None
+        roof["hbm_measured_frac"] = None
+    if valu:
+        rate = valu / (avg_ms * 1e-3)
+        roof["limiter"] = {"bound": "valu", "achieved": round(rate / 1e9, 1),
+                           "peak": round(VALU_PEAK_WAVE_INSTR_PER_S / 1e9, 1),
+                           "unit": "G wave-instructions/s",
+                           "frac": round(rate / VALU_PEAK_WAVE_INSTR_PER_S, 4),
+                           "valu_per_launch": valu}
+    else:
+        roof["limiter"] = None
+
+
+def optimise_leg(args, w, prec_name: str, copy_gbs: float):
+    """The optimisation loop on workload w; returns the result dict."""
     import numpy as np
     import torch
 
     from paper_1303_0107_amd import lbm
 
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 1
-    torch.cuda.set_device(0)
-    if args.workload == BATCH_WORKLOAD:
-        return bench_batch(args)
-    if args.workload == SERVE_WORKLOAD:
-        return bench_serve(args)
-    w = workloads()[args.workload]
     types = w.types()
     N = types.size
     nns = int(np.count_nonzero(types))
     prec = {"f64": lbm.LBM_F64, "f32": lbm.LBM_F32, "f16": lbm.LBM_F32_S_F16,
-            "bf16": lbm.LBM_F32_S_BF16}[args.precision]
-    s_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[args.precision]
-    arith = "f64" if args.precision == "f64" else "f32"
+            "bf16": lbm.LBM_F32_S_BF16}[prec_name]
+    s_bytes = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[prec_name]
+    arith = "f64" if prec_name == "f64" else "f32"
     frac = w.extra.get("frac", 0.01)
     k = 100
-
-    print(f"# workload {w.name} {w.nx}x{w.ny} non-solid {nns} precision {args.precision}",
+    print(f"# workload {w.name} {w.nx}x{w.ny} non-solid {nns} precision {prec_name}",
           file=sys.stderr, flush=True)
-    copy_gbs = copy_ceiling()
     lat = lbm.Lattice(types, w.tau, w.u_peak, precision=prec)
     t0 = time.perf_counter()
     settle_cap = args.settle_cap if args.settle_cap is not None else w.extra.get("cap0", 500000)
@@ -455,6 +494,7 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     timed_steps, launches, sweep_ms = lat.profile_sweeps(False)
+    in_use = lbm.lbm_get_tb_variant(lat.h)
 
     mlups = N * sweeps / wall / 1e6
     bytes_per_step = 18 * s_bytes * nns + N
@@ -465,13 +505,27 @@ def main() -> int:
     n, res, flow, st, r = last
     spread = float((flow.max() - flow.min()) / flow.mean()) if len(flow) else 0.0
     kernel = "tb_kernel" if steps_per_launch > 1.0 else "step_kernel"
-    full = MEASURED_TRAFFIC_PER_FULL_LAUNCH.get((w.name, args.precision, shape))
+    full = MEASURED_TRAFFIC_PER_FULL_LAUNCH.get((w.name, prec_name, in_use))
     per_interval = -(-k // halo)  # launches per check interval
     traffic = round(full + 32 * nns / per_interval) if full else None
+    valu = MEASURED_VALU_PER_FULL_LAUNCH.get((w.name, prec_name, in_use))
+    roof = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": kernel + f" ({prec_name} storage, shape {in_use}: {rows}x64 region, "
+                           f"{halo} steps per launch)",
+        "bytes_per_step": bytes_per_step, "steps_per_launch": round(steps_per_launch, 3),
+        "bytes_per_launch": round(bytes_per_launch), "launches": launches,
+        "avg_launch_us": round(avg_ms * 1e3, 3),
+        "copy_ceiling_GBs": round(copy_gbs, 1),
+        "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
+    }
+    hbm_and_limiter(roof, traffic, valu, avg_ms)
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
         "unit": "MLUPS",
+        "mflups": round(nns * sweeps / wall / 1e6, 2),
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -483,32 +537,159 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": w.name, "nx": w.nx, "ny": w.ny, "non_solid_cells": nns,
-            "tau": w.tau, "u_peak": w.u_peak, "storage": args.precision, "arithmetic": arith,
+            "tau": w.tau, "u_peak": w.u_peak, "storage": prec_name, "arithmetic": arith,
             "step": f"exchange (frac {frac}) + solve to r<{args.tol:g} (cap {args.cap}, "
-                    f"check every {k}) + outlet stats",
-            "sweeps_timed": sweeps, "mflups": round(nns * sweeps / wall / 1e6, 2),
+                    f"check every {k}) + outlet stats (means over two consecutive steps)",
+            "sweeps_timed": sweeps,
             "last_dp": st.dp, "last_theta": st.theta, "last_dg": st.dg,
             "last_spread": spread, "last_residual": res,
+            "last_flux_period_two": st.flow_p2,
             "tuned_shape": {"index": shape, "rows": rows, "halo": halo, "tile": [tw, th]},
+            "shape_in_use": in_use,
             "tune_us_per_step": [round(x * 1e3, 3) for x in tune_ms],
         },
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": kernel + f" ({args.precision} storage, shape {shape}: {rows}x64 region, "
-                               f"{halo} steps per launch)",
-            "bytes_per_step": bytes_per_step, "steps_per_launch": round(steps_per_launch, 3),
-            "bytes_per_launch": round(bytes_per_launch), "launches": launches,
-            "avg_launch_us": round(avg_ms * 1e3, 3),
-            "copy_ceiling_GBs": round(copy_gbs, 1),
-            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
-        },
+        "roofline": roof,
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(types, w, args.cpu_seconds)
     lat.close()
+    return out
+
+
+def sweep_leg(args, w, prec_name: str, steps: int, copy_gbs: float):
+    """Sweeps only (no exchange steps) on workload w after the autotuner:
+    `steps` time steps with residual checks every 100, timed as above."""
+    import numpy as np
+    import torch
+
+    from paper_1303_0107_amd import lbm
+
+    types = w.types()
+    N = types.size
+    nns = int(np.count_nonzero(types))
+    prec = {"f64": lbm.LBM_F64, "f32": lbm.LBM_F32}[prec_name]
+    s_bytes = {"f64": 8, "f32": 4}[prec_name]
+    lat = lbm.Lattice(types, w.tau, w.u_peak, precision=prec)
+    lat.run(2000, 0.0, 100)
+    shape, tune_ms = lat.autotune(400)
+    rows, halo, tw, th = lbm.lbm_tb_variant_info(prec, shape)
+    lat.run(1000, 0.0, 100)
+    torch.cuda.synchronize()
+    lat.profile_sweeps(True)
+    t0 = time.perf_counter()
+    lat.run(steps, 0.0, 100)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    timed_steps, launches, sweep_ms = lat.profile_sweeps(False)
+    in_use = lbm.lbm_get_tb_variant(lat.h)
+    lat.close()
+    bytes_per_step = 18 * s_bytes * nns + N
+    avg_ms = sweep_ms / max(launches, 1)
+    spl = timed_steps / max(launches, 1)
+    achieved = bytes_per_step * spl / (avg_ms * 1e-3) / 1e9
+    full = MEASURED_TRAFFIC_PER_FULL_LAUNCH.get((w.name, prec_name, in_use))
+    per_interval = -(-100 // halo)
+    traffic = round(full + 32 * nns / per_interval) if full else None
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": f"tb_kernel ({prec_name} storage, shape {in_use}: {rows}x64 region, "
+                      f"{halo} steps per launch)",
+            "bytes_per_step": bytes_per_step, "avg_launch_us": round(avg_ms * 1e3, 3),
+            "steps_per_launch": round(spl, 3),
+            "frac_of_copy_ceiling": round(achieved / copy_gbs, 4)}
+    hbm_and_limiter(roof, traffic, MEASURED_VALU_PER_FULL_LAUNCH.get((w.name, prec_name, in_use)),
+                    avg_ms)
+    print(f"# {w.name}: {steps} steps in {wall * 1e3:.1f} ms, shape {in_use}", file=sys.stderr,
+          flush=True)
+    return {"workload": w.name, "storage": prec_name, "steps": steps,
+            "value": round(N * steps / wall / 1e6, 2), "unit": "MLUPS",
+            "mflups": round(nns * steps / wall / 1e6, 2),
+            "us_per_step": round(wall / steps * 1e6, 3), "roofline": roof}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed optimisation iterations")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["f32", "f64", "f16", "bf16"], default="f32",
+                    help="population storage (f64: double storage and arithmetic; f32: float "
+                         "storage, float arithmetic; f16/bf16: 16-bit storage, float arithmetic)")
+    ap.add_argument("--workload", default="distributor-1024x512-L3")
+    ap.add_argument("--legs", default="main,channel,serve",
+                    help="comma list: main (the workload's optimisation loop, or sweeps for a "
+                         "channel), channel (1024x512 all-fluid sweeps), serve (short serving "
+                         "run)")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--cap", type=int, default=200000, help="step cap per solve")
+    ap.add_argument("--settle-cap", type=int, default=None,
+                    help="step cap of the untimed solve from rest (default: workload's)")
+    ap.add_argument("--tune-steps", type=int, default=256,
+                    help="steps per autotuner trial")
+    ap.add_argument("--sweep-steps", type=int, default=20000,
+                    help="timed time steps of a sweep leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=10000,
+                    help="time steps per benchmark step of the batched workload")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="arrival window of the serving workload run on its own")
+    ap.add_argument("--serve-leg-seconds", type=float, default=20.0,
+                    help="arrival window of the serving leg of the default run")
+    ap.add_argument("--hbm-budget-gb", type=float, default=32.0)
+    ap.add_argument("--max-sessions", type=int, default=64)
+    ap.add_argument("--quantum", type=int, default=20)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    if args.workload == BATCH_WORKLOAD:
+        return bench_batch(args)
+    if args.workload == SERVE_WORKLOAD:
+        return bench_serve(args)
+    legs = {x.strip() for x in args.legs.split(",") if x.strip()}
+    w = workloads()[args.workload]
+    copy_gbs = copy_ceiling()
+    bad = 0
+    if w.kind == "channel":
+        leg = sweep_leg(args, w, args.precision, args.sweep_steps, copy_gbs)
+        out = {"metric": METRIC, "value": leg["value"], "unit": "MLUPS", "mflups": leg["mflups"],
+               "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": leg["us_per_step"] * 1e-3,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64" if args.precision == "f64" else "f32", "data": "synthetic",
+               "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "storage": args.precision,
+                          "step": "one time step (sweeps only)"},
+               "roofline": leg["roofline"]}
+    else:
+        out = optimise_leg(args, w, args.precision, copy_gbs)
+    if "channel" in legs and w.kind != "channel":
+        from paper_1303_0107_amd import inputs as I
+        out["channel"] = sweep_leg(args, I.CHANNEL_1024x512, "f32", args.sweep_steps, copy_gbs)
+    if "serve" in legs:
+        srv, bad = serve_leg(args, args.serve_rate, args.serve_leg_seconds)
+        out["latency_ms"] = srv["config"]["latency_ms"]
+        out["serving"] = {"value": srv["value"], "unit": "MLUPS", "mflups": srv["config"]["mflups"],
+                          "requests": srv["config"]["requests"],
+                          "arrivals": srv["config"]["arrivals"], "mix": srv["config"]["mix"],
+                          "failed": srv["config"]["failed"],
+                          "busy_seconds": srv["config"]["busy_seconds"],
+                          "event_seconds": srv["config"]["event_seconds"],
+                          "sweep_seconds": srv["config"]["sweep_seconds"],
+                          "admit_seconds": srv["config"]["admit_seconds"],
+                          "wall_seconds": srv["config"]["wall_seconds"]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w.types(), w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    return 0
+    return 0 if not bad else 1
 
 
 if __name__ == "__main__":

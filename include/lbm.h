@@ -269,7 +269,11 @@ int lbm_set_state(lbm_handle *h, const double *f, size_t n);
 
 /* Device bytes a handle for d would allocate (0 if d is invalid), each
  * buffer counted in the size class it is allocated in (its size rounded up
- * to a multiple of 1/8 of its power of two). */
+ * to a multiple of 1/8 of its power of two): the buffers made at creation,
+ * those the first exchange step and outlet statistics make, with the
+ * candidate lists at their initial capacity (max(4096, nx*ny/16) per kind).
+ * A lattice with more interface cells of one kind than that grows its lists
+ * on an exchange step and then holds more than this count. */
 size_t lbm_footprint_bytes(const lbm_geometry_desc *d);
 
 /* Release a handle (NULL is ignored).  The call waits for the handle's
@@ -332,6 +336,14 @@ int lbm_tb_variant_kind(int32_t precision, int32_t variant, int32_t *kind,
  * only, never results.
  * Errors: LBM_EINVAL (NULL handle, variant out of range), LBM_EHIP. */
 int lbm_set_tb_variant(lbm_handle *h, int32_t variant);
+
+/* The region shape the handle's sweeps use now: the last lbm_set_tb_variant
+ * or lbm_autotune choice, or, after an exchange step pushed the autotuned
+ * shape's active tiles past one round of workgroups, the fastest timed shape
+ * whose tiles still fit (the autotuned shape is taken back once it fits
+ * again).  -1 when temporal blocking is off (one launch per step).
+ * Errors: LBM_EINVAL (NULL argument). */
+int lbm_get_tb_variant(lbm_handle *h, int32_t *variant);
 
 /*
  * Autotuner: time every compiled shape on `trial_steps` (>= 1) real time

@@ -83,6 +83,7 @@ def _load():
         lib.orc_shape_update.argtypes = [i32, i32, P, P, P, P, f64, u64, i32, i32, i32, i32,
                                          P, P, P, i32, P, P, P, P]
         lib.orc_num_threads.restype = i32
+        lib.orc_set_num_threads.argtypes = [i32]
         lib.orc_residual.argtypes = [i32, i32, P, P, P, P, P]
         lib.orc_residual.restype = f64
         _lib = lib
@@ -127,6 +128,11 @@ def splitmix64(state: int) -> int:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the per-cell passes (results do not depend on it)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def residual(types: np.ndarray, ux, uy, ux_prev, uy_prev) -> float:

@@ -367,6 +367,7 @@ struct lbm_handle {
     hipEvent_t tile_copied = nullptr;  // recorded after the last upload
     int n_tiles = 0;
     int tb_variant = 0;         // region shape (index into the compiled shapes)
+    int tuned_variant = -1;     // the last autotuner's choice (-1: none, or overridden)
     // Per-shape ms/step of the last lbm_autotune (empty before one), whether
     // its choice then had every tile resident at once, and the device's CU
     // count and LDS per CU (how many workgroups of a shape run at once).
@@ -457,6 +458,9 @@ size_t max_tile_count(int nx, int ny, int precision) {
     return m;
 }
 
+// Initial capacity of each exchange-step candidate list.
+int64_t initial_cand_cap(size_t N) { return std::max<int64_t>(4096, (int64_t)(N / 16)); }
+
 size_t footprint(int nx, int ny, int precision) {
     const int pitch = pitch_for(nx);
     const size_t plane = (size_t)ny * pitch, N = (size_t)nx * ny;
@@ -472,6 +476,16 @@ size_t footprint(int nx, int ny, int precision) {
     b += c(std::max((size_t)sweep_blocks(nx, ny), ntiles) * 4 * sizeof(double));
     b += c(ntiles * sizeof(int32_t));
     b += c(3 * N * sizeof(double));          // macro field (exchange step)
+    // exchange step, allocated on the first one: the two candidate lists at
+    // their initial capacity, the selection scratch and the selections (each
+    // at most that capacity); the lists grow when a lattice has more
+    // interface cells than N/16 per kind, and the count then exceeds this
+    const int64_t cap = initial_cand_cap(N);
+    b += c((size_t)cap * 2 * (2 * sizeof(uint64_t) + sizeof(int32_t)));
+    b += c(select_scratch_bytes(cap));
+    b += c((size_t)cap * (sizeof(double) + 2 * sizeof(int32_t)));
+    // the outlet sums of lbm_outlet_stats
+    b += c((size_t)(2 * (2 * ny + 5) + 1) * sizeof(double));
     return b;
 }
 
@@ -574,26 +588,20 @@ size_t resident_tiles(const lbm_handle *h, int variant) {
     return (size_t)h->cus * std::max<size_t>(1, h->lds_per_cu / std::max<size_t>(lds, 1));
 }
 
-// The autotuner's timings hold while its shape's tiles all run in one round.
-// When an exchange step has pushed them past that, take the fastest timed
-// shape whose tiles still fit (the shape never changes results).
+// After an exchange step: the autotuned shape while its tiles all run in one
+// round of workgroups, else the fastest timed shape whose tiles do (the
+// shape never changes results); see fitted_shape.
 void refit_shape(lbm_handle *h) {
     const int nv = (int)h->tune_ms.size();
-    if (nv == 0 || !h->use_tb || !h->tune_fit) return;
-    if ((size_t)h->n_tiles <= resident_tiles(h, h->tb_variant)) return;
-    std::vector<int> order(nv);
-    for (int v = 0; v < nv; ++v) order[v] = v;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return h->tune_ms[a] < h->tune_ms[b]; });
-    for (int v : order) {
-        const size_t n = tile_list(h, tile_width(h->precision, v), tile_height(h->precision, v)).size();
-        if (n <= resident_tiles(h, v)) {
-            if (v != h->tb_variant) {
-                h->tb_variant = v;
-                rebuild_tiles(h);
-            }
-            return;
-        }
+    if (nv == 0 || !h->use_tb || !h->tune_fit || h->tuned_variant < 0) return;
+    std::vector<size_t> resident(nv);
+    for (int v = 0; v < nv; ++v) resident[v] = resident_tiles(h, v);
+    const int v = fitted_shape(h->tuned_variant, h->tune_ms, resident, [&](int s) {
+        return tile_list(h, tile_width(h->precision, s), tile_height(h->precision, s)).size();
+    });
+    if (v != h->tb_variant) {
+        h->tb_variant = v;
+        rebuild_tiles(h);
     }
 }
 
@@ -1596,7 +1604,7 @@ int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
         }
         ensure_pinned(h, 64 * sizeof(double));
         // candidate lists: 2 x (u64 key, u64 hash, i32 idx) per entry
-        if (h->cand_cap == 0) h->cand_cap = std::max<int64_t>(4096, (int64_t)(N / 16));
+        if (h->cand_cap == 0) h->cand_cap = initial_cand_cap(N);
         unsigned long long *counters = h->red.as<unsigned long long>() + 32;
         int *err = reinterpret_cast<int *>(h->red.as<unsigned long long>() + 36);
         unsigned long long cnt[2] = {0, 0};
@@ -1855,6 +1863,13 @@ int lbm_precision_info(int32_t precision, int32_t *storage_bytes, int32_t *arith
     return LBM_OK;
 }
 
+int lbm_get_tb_variant(lbm_handle *h, int32_t *variant) {
+    g_error.clear();
+    if (!h || !variant) return fail(LBM_EINVAL, "null argument");
+    *variant = h->use_tb ? h->tb_variant : -1;
+    return LBM_OK;
+}
+
 int lbm_set_tb_variant(lbm_handle *h, int32_t variant) {
     g_error.clear();
     if (!h) return fail(LBM_EINVAL, "null handle");
@@ -1863,6 +1878,7 @@ int lbm_set_tb_variant(lbm_handle *h, int32_t variant) {
     try {
         HIP_TRY(hipSetDevice(h->device));
         h->tb_variant = variant;
+        h->tuned_variant = -1;
         h->tune_ms.clear();  // an explicit choice is kept through exchange steps
         rebuild_tiles(h);
     } catch (const HipFail &e) {
@@ -1901,6 +1917,7 @@ int lbm_autotune(lbm_handle *h, int32_t trial_steps, int32_t *best, double *ms,
             }
         }
         h->tb_variant = bv;
+        h->tuned_variant = bv;
         rebuild_tiles(h);
         h->tune_ms = times;
         h->tune_fit = (size_t)h->n_tiles <= resident_tiles(h, bv);

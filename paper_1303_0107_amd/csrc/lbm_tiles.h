@@ -4,6 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 namespace lbm {
@@ -30,6 +31,27 @@ inline std::vector<int32_t> dealt_tiles(const std::vector<int32_t> &list, size_t
     for (size_t k = 0; k < 8; ++k)
         for (size_t j = 0; j < xcd[k].size(); ++j) out[8 * j + k] = xcd[k][j];
     return out;
+}
+
+// Region shape to run after the mask has changed.  The autotuner's timings
+// (ms[v] per step for shape v) hold while a shape's active tiles all run in
+// one round of workgroups: tiles(v) <= resident[v], the workgroups of shape v
+// the chip holds at once (CUs x workgroups per CU by LDS).  The tuned shape is
+// kept (or taken back) whenever it fits; otherwise the fastest timed shape
+// that fits; the tuned shape when none does.  tiles(v) is called only for
+// shapes that are considered, in order of their timings.
+template <typename TileCount>
+int fitted_shape(int tuned, const std::vector<double> &ms,
+                 const std::vector<size_t> &resident, TileCount tiles) {
+    const int nv = (int)ms.size();
+    if (tuned < 0 || tuned >= nv || (int)resident.size() != nv) return tuned;
+    if (tiles(tuned) <= resident[tuned]) return tuned;
+    std::vector<int> order(nv);
+    for (int v = 0; v < nv; ++v) order[v] = v;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return ms[a] < ms[b]; });
+    for (int v : order)
+        if (v != tuned && tiles(v) <= resident[v]) return v;
+    return tuned;
 }
 
 }  // namespace lbm

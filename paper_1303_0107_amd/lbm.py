@@ -152,6 +152,7 @@ def load() -> ctypes.CDLL:
         "lbm_server_destroy": (None, [H]),
         "lbm_precision_info": (ctypes.c_int, [i32, P, P]),
         "lbm_outlet_stats_noalloc": (ctypes.c_int, [H, P, i32, P]),
+        "lbm_get_tb_variant": (ctypes.c_int, [H, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -342,6 +343,13 @@ def lbm_tb_variant_kind(precision: int, variant: int):
     _check(load().lbm_tb_variant_kind(int(precision), int(variant),
                                       *[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)
+
+
+def lbm_get_tb_variant(h) -> int:
+    """The region shape in use (-1: one launch per step)."""
+    v = ctypes.c_int32()
+    _check(load().lbm_get_tb_variant(h, ctypes.byref(v)))
+    return v.value
 
 
 def lbm_set_tb_variant(h, variant: int) -> None:

@@ -1,12 +1,14 @@
 """Condense rocprofv3 CSV output into the short text summaries kept here.
 
 usage: python -m paper_1303_0107_amd.rocprof_summary STATS_CSV [FETCH_CSV WRITE_CSV] --cmd "..." --kernel SUBSTR
-           [--copy-bytes N] [--algo-bytes N]
+           [--copy-bytes N] [--algo-bytes N] [--pmc CSV ...]
 
 STATS_CSV is a --kernel-trace --stats *_kernel_stats.csv; FETCH_CSV/WRITE_CSV
 are --pmc FETCH_SIZE / WRITE_SIZE *_counter_collection.csv files of the same
 program.  The counters are scaled by what they read for the plain copy kernel
 (__amd_rocclr_copyBuffer of --copy-bytes bytes, reads and writes each).
+Each --pmc CSV (any other counters) adds, per matching kernel and grid size,
+the mean of every counter it holds per dispatch.
 """
 import argparse
 import collections
@@ -52,6 +54,7 @@ def main():
     ap.add_argument("--kernel", required=True)
     ap.add_argument("--copy-bytes", type=int, default=1 << 28)
     ap.add_argument("--algo-bytes", type=int, default=0)
+    ap.add_argument("--pmc", action="append", default=[])
     a = ap.parse_args()
     print(f"command: {a.cmd}")
     print()
@@ -59,6 +62,18 @@ def main():
     for r in csv.DictReader(open(a.stats)):
         print(f"{short(r['Name'])[:72]:72s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.3f} "
               f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}")
+    for path in a.pmc:
+        print()
+        print(f"counters per dispatch (mean) from {path.split('/')[-1]}:")
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        for r in csv.DictReader(open(path)):
+            if a.kernel in r["Kernel_Name"]:
+                agg[(r["Kernel_Name"], int(r["Grid_Size"]))][r["Counter_Name"]].append(
+                    float(r["Counter_Value"]))
+        for (k, g), cs in sorted(agg.items(), key=lambda kv: -len(next(iter(kv[1].values())))):
+            n = len(next(iter(cs.values())))
+            vals = ", ".join(f"{c} {sum(v) / len(v):.4g}" for c, v in sorted(cs.items()))
+            print(f"{short(k)[:72]} grid {g} ({n} dispatches): {vals}")
     if not a.fetch:
         return
     print()

@@ -16,7 +16,7 @@ EXPECTED = {
     "lbm_batch_configure", "lbm_batch_tune", "lbm_batch_info", "lbm_batch_destroy",
     "lbm_batch_set_graphs", "lbm_state_digest", "lbm_server_create", "lbm_server_submit",
     "lbm_server_poll", "lbm_server_drain", "lbm_server_stats_get", "lbm_server_destroy",
-    "lbm_precision_info", "lbm_outlet_stats_noalloc",
+    "lbm_precision_info", "lbm_outlet_stats_noalloc", "lbm_get_tb_variant",
 }
 
 

@@ -28,14 +28,35 @@ def test_more_than_one_gpu_is_refused():
 def test_cpu_baseline_fields():
     wl = I.CORRECTNESS_128x64
     out = bench.cpu_baseline(wl.types(), wl, 0.2)
-    assert set(out) == {"value", "unit", "cores", "kind", "sample"}
+    assert {"value", "unit", "cores", "kind", "sample"} <= set(out)
     assert out["unit"] == "MLUPS" and out["kind"] == "oracle"
     assert out["value"] > 0 and out["cores"] >= 1
     assert wl.name in out["sample"]
+    one = out["single_thread"]
+    assert one["cores"] == 1 and one["value"] > 0 and one["unit"] == "MLUPS"
+    assert isinstance(out["cpu_model"], str) and out["cpu_model"]
+    assert 0 < out["mflups"] < out["value"]
+
+
+def test_limiter_and_measured_hbm_fields():
+    roof = {}
+    bench.hbm_and_limiter(roof, 8.5e6, 1.0e6, 0.0135)
+    assert roof["hbm_measured_GBs"] == pytest.approx(8.5e6 / 13.5e-6 / 1e9, rel=1e-3)
+    assert roof["hbm_measured_frac"] == pytest.approx(roof["hbm_measured_GBs"] / 8000, rel=1e-3)
+    lim = roof["limiter"]
+    assert lim["bound"] == "valu" and lim["peak"] == pytest.approx(614.4)
+    assert lim["frac"] == pytest.approx(1.0e6 / 13.5e-6 / 614.4e9, rel=1e-3)
+    roof = {}
+    bench.hbm_and_limiter(roof, None, None, 0.0135)
+    assert roof["hbm_measured_GBs"] is None and roof["limiter"] is None
 
 
 def test_measured_traffic_names_compiled_shapes():
     names = set(bench.workloads())
+    for (workload, prec, shape), valu in bench.MEASURED_VALU_PER_FULL_LAUNCH.items():
+        assert workload in names
+        assert 0 <= shape < lbm.lbm_tb_variant_count(PREC[prec])
+        assert valu > 0
     for (workload, prec, shape), full in bench.MEASURED_TRAFFIC_PER_FULL_LAUNCH.items():
         assert workload in names
         assert 0 <= shape < lbm.lbm_tb_variant_count(PREC[prec])
