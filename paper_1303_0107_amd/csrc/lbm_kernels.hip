@@ -133,7 +133,9 @@ struct OffsetCell {
                                                   const SweepArgs<T> &a, double &mass,
                                                   double &ux_out, double &uy_out) {
 #pragma clang fp contract(on)
-        if (type == kInlet) {
+        if (type == kFluid) {
+            // no closure (the common case, tested first)
+        } else if (type == kInlet) {
             const CT s = (d[0] + (d[2] + d[4])) + CT(2) * (d[3] + (d[6] + d[7]));
             const CT dr = (s + bx) * recip(CT(1) - bx);
             const CT ru = (CT(1) + dr) * bx;
@@ -182,11 +184,13 @@ struct OffsetCell {
         // mirror-symmetric order, so a y-reflection maps each increment onto
         // its mirror image bit for bit.
         CT t[9];
+        // A + B = (4.5 cu + 3) cu - 1.5 u.u and A - B = (4.5 cu - 3) cu - 1.5 u.u,
+        // two multiply-adds each.
         auto incr_pair = [&](int i, int j, PT cu, CT w) {
-            const PT A = PT(4.5) * cu * cu - puu15;
-            const PT B = PT(3) * cu;
-            t[i] = w * (dr + rho * (CT)(A + B)) - d[i];
-            t[j] = w * (dr + rho * (CT)(A - B)) - d[j];
+            const PT hp = PT(4.5) * cu + PT(3), hm = PT(4.5) * cu - PT(3);
+            const PT ApB = hp * cu - puu15, AmB = hm * cu - puu15;
+            t[i] = w * (dr + rho * (CT)ApB) - d[i];
+            t[j] = w * (dr + rho * (CT)AmB) - d[j];
         };
         const CT w1 = CT(1) / CT(9), w5 = CT(1) / CT(36);
         incr_pair(1, 3, pux, w1);

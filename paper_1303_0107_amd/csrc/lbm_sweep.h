@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -58,6 +60,42 @@ __device__ __forceinline__ size_t general_src(uint32_t cw, int i, int col, int r
     }
     return (size_t)pop * plane + (size_t)rs * stride + (col - kCx[i]);
 }
+
+// LDS stores of one region cell in a step: plane i of copy b sits at
+// (2i + b) * PL elements, reached from one of three LDS addresses (planes 0-3,
+// 4-7, 8), so that every store's remaining offset fits the 16-bit immediate
+// of an LDS instruction.  The addresses are made opaque once per launch so
+// that they stay in registers instead of being recomputed at every step.
+template <typename T, int PL>
+struct StoreBases {
+    // the stored bits (the 16-bit formats are classes without an assignment
+    // in the LDS address space)
+    using Bits = typename std::conditional<
+        sizeof(T) == 8, uint64_t,
+        typename std::conditional<sizeof(T) == 4, uint32_t, uint16_t>::type>::type;
+    using LdsBits = __attribute__((address_space(3))) Bits;
+    LdsBits *b[3];
+    __device__ __forceinline__ void set(T *L, int pos) {
+        LdsBits *p = (LdsBits *)reinterpret_cast<Bits *>(L + pos);
+        b[0] = p;
+        b[1] = p + 8 * PL;
+        b[2] = p + 16 * PL;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(b[k]));
+    }
+    // Population i into copy C.
+    template <int C>
+    __device__ __forceinline__ void put(int i, T v) const {
+        Bits w;
+        __builtin_memcpy(&w, &v, sizeof(T));
+        if (i < 4)
+            b[0][(2 * i + C) * PL] = w;
+        else if (i < 8)
+            b[1][(2 * (i - 4) + C) * PL] = w;
+        else
+            b[2][C * PL] = w;
+    }
+};
 
 // Sum of NV doubles over a block of NT threads into thread 0, in a fixed
 // order (wave butterflies, then waves in index order).
@@ -204,6 +242,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
     uint32_t cw[CPT];
     int depth[CPT];
     const T *src[CPT][9];  // LDS address of each pull in copy 0
+    StoreBases<T, PL> dst[CPT];
     UinT<T> uin[CPT];      // inlet velocity of the thread's cells, read once per launch
     T v[CPT][9];
     size_t n[CPT];
@@ -242,6 +281,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
             const int e = wall ? 2 * kOpp[i] * PL + pos : 2 * i * PL + pos - kCy[i] * RW - kCx[i];
             src[c][i] = L + e;
         }
+        dst[c].set(L, pos);
     }
     // the whole workgroup leaves when the run has ended (the flag, read with
     // the region, is the same for every lane)
@@ -286,7 +326,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
                 if (CHECK) check_terms(a, n, mass, ux, uy, part);
             } else {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) L[(2 * i + 1 - B) * PL + pos] = Cell::store(f[i]);
+                for (int i = 0; i < 9; ++i) dst[c].template put<1 - B>(i, Cell::store(f[i]));
             }
         }
         if (last) return true;
@@ -547,6 +587,7 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
     const int n_all = cls_base[0];
     uint32_t ent[CPT];
     const T *src[CPT][9];  // LDS address of each pull of the thread's entries in copy 0
+    StoreBases<T, PL> dst[CPT];
     UinT<T> uin[CPT];      // inlet velocity of the thread's entries, read once per launch
 #pragma unroll
     for (int m = 0; m < CPT; ++m) {
@@ -554,6 +595,7 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
         ent[m] = j < n_all ? list[j] : 0u;
         const uint32_t c = ent[m] >> 16;
         const int pos = (int)(ent[m] & 0xffffu);
+        dst[m].set(L, pos);
         uin[m] = (j < n_all && cell_type(c) == kInlet) ? a.uin[oy + pos / RW] : UinT<T>(0);
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -604,7 +646,7 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
                 if (CHECK) check_terms(a, n, mass, ux, uy, part);
             } else {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) L[(2 * i + 1 - B) * PL + pos] = Cell::store(f[i]);
+                for (int i = 0; i < 9; ++i) dst[m].template put<1 - B>(i, Cell::store(f[i]));
             }
         }
         if (last) return true;
