@@ -387,6 +387,8 @@ def serve_leg(args, rate: float, seconds: float):
             "admit_seconds": round(st.admit_seconds, 3),
             "sweep_seconds": round(st.sweep_seconds, 3),
             "event_seconds": round(st.event_seconds, 3),
+            "exchange_seconds": round(st.exchange_seconds, 3), "exchanges": st.exchanges,
+            "exchange_calls": st.exchange_calls,
             "wall_seconds": round(wall, 3), "peak_bytes": st.peak_bytes,
             "mflups": round(st.nonsolid_cell_steps / wall / 1e6, 2),
         },

@@ -246,6 +246,18 @@ int lbm_outlet_stats_noalloc(lbm_handle *h, double *flow, int32_t flow_cap, lbm_
 int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
                      const double *rho_ux_uy, lbm_shape_result *r);
 
+/* The exchange step of lbm_shape_update on n distinct handles at once (each
+ * with its own parameters, keys from its current state), with the work of
+ * all of them issued before each of the step's two waits for the device
+ * instead of two waits per handle: for a server whose sessions reach their
+ * exchange steps together (Sec. 2.3 steps 3-4 for many shapes).  Each
+ * handle's result is exactly that of lbm_shape_update.  status[k] receives
+ * handle k's status; the call returns the most negative of them (LBM_OK when
+ * all succeeded).  Errors: LBM_EINVAL (NULL arrays, n < 0, a handle listed
+ * twice), or per handle those of lbm_shape_update. */
+int lbm_shape_update_many(lbm_handle *const *hs, const lbm_shape_params *ps, int32_t n,
+                          lbm_shape_result *rs, int32_t *status);
+
 /* Logical indices of the cells the last lbm_shape_update made solid
  * (removed) and fluid (added), in selection order.  Returns the count k_eff
  * (>= 0) or LBM_EINVAL when cap < k_eff. */
@@ -511,6 +523,9 @@ typedef struct {
     double sweep_seconds;    /*           batched sweeps (incl. batch rebuilds) */
     double event_seconds;    /*           exchange steps and completions        */
     size_t peak_bytes;       /* largest admitted footprint sum                  */
+    double exchange_seconds; /* of event_seconds: exchange steps               */
+    int64_t exchanges;       /* exchange steps taken                            */
+    int64_t exchange_calls;  /* lbm_shape_update_many calls that took them      */
 } lbm_server_stats;
 
 typedef struct lbm_server lbm_server;

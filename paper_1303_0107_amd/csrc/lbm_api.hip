@@ -1577,169 +1577,307 @@ int lbm_outlet_stats_noalloc(lbm_handle *h, double *flow, int32_t flow_cap, lbm_
     return LBM_OK;
 }
 
-int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
-                     const double *rho_ux_uy, lbm_shape_result *r) {
-    g_error.clear();
+}  // extern "C"
+
+namespace {
+
+// One exchange step (Steps 3-4 of Sec. 2.3) split into the phases between
+// which the host waits for the device, so that lbm_shape_update_many can run
+// each phase for many handles before waiting once.
+struct Exchange {
+    lbm_handle *h = nullptr;
+    lbm_shape_params p{};
+    const double *field = nullptr;  // host override of (rho, ux, uy), or NULL
+    lbm_shape_result *r = nullptr;
+    int status = LBM_OK;
+    int64_t keff = 0, nf = 0;
+    unsigned long long cnt[2] = {0, 0};
+    size_t rb_al = 0;  // pinned offset of the selection kernels' error flag
+};
+
+int exchange_check(lbm_handle *h, const lbm_shape_params *p, lbm_shape_result *r) {
     if (!h || !p || !r) return fail(LBM_EINVAL, "null argument");
-    if (!(p->frac >= 0.0 && p->frac <= 1.0))
-        return fail(LBM_EINVAL, "frac must be in [0, 1]");
-    if (p->band_x < 1 || p->band_y < 1 || 2 * p->band_x >= h->nx ||
-        2 * p->band_y >= h->ny)
+    if (!(p->frac >= 0.0 && p->frac <= 1.0)) return fail(LBM_EINVAL, "frac must be in [0, 1]");
+    if (p->band_x < 1 || p->band_y < 1 || 2 * p->band_x >= h->nx || 2 * p->band_y >= h->ny)
         return fail(LBM_EINVAL, "band_x, band_y must be >= 1 and leave an interior");
     if (p->criterion != LBM_CRIT_PAPER && p->criterion != LBM_CRIT_SPEED)
         return fail(LBM_EINVAL, "unknown criterion");
     if (p->reinit != LBM_WARM && p->reinit != LBM_COLD)
         return fail(LBM_EINVAL, "unknown reinit mode");
-    std::memset(r, 0, sizeof *r);
-    const size_t N = h->N();
-    try {
-        HIP_TRY(hipSetDevice(h->device));
-        h->macro.ensure(3 * N * sizeof(double));
-        double *m = h->macro.as<double>();
-        if (rho_ux_uy) {
-            HIP_TRY(hipMemcpyAsync(m, rho_ux_uy, 3 * N * sizeof(double),
-                                   hipMemcpyHostToDevice, h->stream));
-        } else {
-            macro_dispatch(h);
-        }
-        ensure_pinned(h, 64 * sizeof(double));
-        // candidate lists: 2 x (u64 key, u64 hash, i32 idx) per entry
-        if (h->cand_cap == 0) h->cand_cap = initial_cand_cap(N);
-        unsigned long long *counters = h->red.as<unsigned long long>() + 32;
-        int *err = reinterpret_cast<int *>(h->red.as<unsigned long long>() + 36);
-        unsigned long long cnt[2] = {0, 0};
-        for (int attempt = 0; attempt < 2; ++attempt) {
-            const int64_t cap = h->cand_cap;
-            h->cand.ensure((size_t)cap * 2 * (2 * sizeof(uint64_t) + sizeof(int32_t)));
-            uint64_t *kf = h->cand.as<uint64_t>();
-            uint64_t *hf = kf + cap, *ks = kf + 2 * cap, *hs = kf + 3 * cap;
-            int32_t *if_ = reinterpret_cast<int32_t *>(kf + 4 * cap), *is = if_ + cap;
-            // counters[0..3] and the error flag (counters + 4) in one fill
-            HIP_TRY(hipMemsetAsync(counters, 0, 5 * sizeof(unsigned long long), h->stream));
-            KeysArgs ka;
-            ka.types = h->types.as<uint8_t>();
-            ka.rho = m;
-            ka.ux = m + N;
-            ka.uy = m + 2 * N;
-            ka.nx = h->nx;
-            ka.ny = h->ny;
-            ka.band_x = p->band_x;
-            ka.band_y = p->band_y;
-            ka.criterion = p->criterion;
-            ka.seed = p->seed;
-            ka.cap = cap;
-            ka.count_f = counters;
-            ka.count_s = counters + 1;
-            ka.error = err;
-            ka.kf = kf;
-            ka.hf = hf;
-            ka.ks = ks;
-            ka.hs = hs;
-            ka.if_ = if_;
-            ka.is = is;
-            HIP_TRY(launch_keys(ka, h->stream));
-            HIP_TRY(hipMemcpyAsync(h->pinned, counters, 5 * sizeof(unsigned long long),
-                                   hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(hipStreamSynchronize(h->stream));
-            const unsigned long long *pc = reinterpret_cast<unsigned long long *>(h->pinned);
-            cnt[0] = pc[0];
-            cnt[1] = pc[1];
-            const int e = *reinterpret_cast<const int *>(pc + 4);
-            if (e != 0) return fail(LBM_EINVAL, "NaN or negative exchange key");
-            const int64_t need = (int64_t)std::max(cnt[0], cnt[1]);
-            if (need <= cap) break;
-            h->cand_cap = need;  // grow and recompute
-            h->cand.reset();
-        }
-        const int64_t cap = h->cand_cap;
-        if ((int64_t)std::max(cnt[0], cnt[1]) > cap)
-            return fail(LBM_EHIP, "candidate count changed between passes");
-        uint64_t *kf = h->cand.as<uint64_t>();
-        uint64_t *hf = kf + cap, *ks = kf + 2 * cap, *hs = kf + 3 * cap;
-        int32_t *if_ = reinterpret_cast<int32_t *>(kf + 4 * cap), *is = if_ + cap;
-        const int64_t nf = h->n_fluid;
-        int64_t K = (int64_t)std::floor(p->frac * (double)nf);
-        if (K < 1) K = 1;
-        const int64_t keff = std::min<int64_t>(K, std::min<int64_t>(cnt[0], cnt[1]));
-        r->n_cand_fluid = (int64_t)cnt[0];
-        r->n_cand_solid = (int64_t)cnt[1];
-        r->n_fluid_before = nf;
-        std::vector<int32_t> rem(keff), add(keff);
-        double mass_removed = 0.0;
-        if (keff > 0) {
-            // sel: the removed cells' densities, then the removed and the
-            // added cell lists (the layout the pinned readback mirrors)
-            h->sel.ensure((size_t)keff * (sizeof(double) + 2 * sizeof(int32_t)));
-            double *rrho = h->sel.as<double>();
-            int32_t *srem = reinterpret_cast<int32_t *>(rrho + keff), *sadd = srem + keff;
-            h->select_tmp.ensure(select_scratch_bytes(keff));
-            HIP_TRY(launch_select_pair(kf, hf, if_, (int64_t)cnt[0], ks, hs, is, (int64_t)cnt[1],
-                                       keff, srem, sadd, h->select_tmp.p, keff, err,
-                                       h->stream));
-            HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, rrho, m,
-                                h->stream));
-            if (p->reinit == LBM_WARM)  // removed and added cells, adjacent in sel
-                with_storage(h->precision,
-                             [&](auto t) { zero_cells<decltype(t)>(h, srem, 2 * (int)keff); });
-            // the selections and removed densities, then the error flag the
-            // selection kernels may have set
-            const size_t rb = (size_t)keff * (sizeof(double) + 2 * sizeof(int32_t));
-            const size_t rb_al = (rb + 7) / 8 * 8;
-            ensure_pinned(h, rb_al + sizeof(double));
-            HIP_TRY(hipMemcpyAsync(h->pinned, rrho, rb, hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(hipMemcpyAsync(reinterpret_cast<char *>(h->pinned) + rb_al, err, sizeof(int),
-                                   hipMemcpyDeviceToHost, h->stream));
-            HIP_TRY(hipStreamSynchronize(h->stream));
-            if (*reinterpret_cast<const int *>(reinterpret_cast<const char *>(h->pinned) + rb_al))
-                return fail(LBM_EHIP, "the selection kernels found an inconsistent candidate list");
-            const double *rr = h->pinned;
-            const int32_t *ix = reinterpret_cast<const int32_t *>(h->pinned + keff);
-            std::memcpy(rem.data(), ix, keff * sizeof(int32_t));
-            std::memcpy(add.data(), ix + keff, keff * sizeof(int32_t));
-            for (int64_t k = 0; k < keff; ++k) mass_removed += rr[k];  // selection order
-        }
-        if (p->reinit == LBM_COLD) {
-            with_storage(h->precision, [&](auto t) { reset_all<decltype(t)>(h); });
-        }
-        HIP_TRY(launch_build_cells(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), h->nx,
-                                   h->ny, h->pitch, h->flags, h->stream));
-        // Constant volume by construction (k_eff fluid cells out, k_eff
-        // solid cells in); checked on the host mirror as the flips apply:
-        // every removed cell must have been fluid and every added one solid,
-        // each listed once.
-        int64_t nf_after = nf;
-        for (int64_t k = 0; k < keff; ++k) {
-            uint8_t &tr = h->host_types[rem[k]];
-            nf_after -= tr == LBM_FLUID ? 1 : 0;
-            tr = tr == LBM_FLUID ? (uint8_t)LBM_SOLID : (uint8_t)0xff;
-        }
-        for (int64_t k = 0; k < keff; ++k) {
-            uint8_t &ta = h->host_types[add[k]];
-            nf_after += ta == LBM_SOLID ? 1 : 0;
-            ta = ta == LBM_SOLID ? (uint8_t)LBM_FLUID : (uint8_t)0xff;
-        }
-        for (int64_t k = 0; k < keff; ++k)
-            if (h->host_types[rem[k]] == 0xff || h->host_types[add[k]] == 0xff) nf_after = -1;
-        h->last_removed.assign(rem.begin(), rem.end());
-        h->last_added.assign(add.begin(), add.end());
-        if (keff > 0) {
-            tilings_flip(h, rem, add);
-            rebuild_tiles(h);
-            refit_shape(h);
-            ++h->mask_version;
-        }
-        r->k_eff = (int32_t)keff;
-        r->n_fluid_after = nf_after;
-        r->mass_removed = mass_removed;
-        r->mass_added = (double)keff;
-        if (nf_after != nf)
-            return fail(LBM_EHIP, "fluid volume changed by the exchange step");
-    } catch (const HipFail &e) {
-        return guard_hip(e);
-    } catch (const std::bad_alloc &) {
-        return fail(LBM_ENOMEM, "device allocation failed");
-    }
     return LBM_OK;
+}
+
+unsigned long long *exchange_counters(lbm_handle *h) {
+    return h->red.as<unsigned long long>() + 32;
+}
+int *exchange_error(lbm_handle *h) {
+    return reinterpret_cast<int *>(h->red.as<unsigned long long>() + 36);
+}
+
+// Phase 1: the field (the current state's moments, or the override), then the
+// candidates and their keys; the counts and the error flag are copied to the
+// pinned staging.  No wait.
+void exchange_keys(Exchange &e) {
+    lbm_handle *h = e.h;
+    const size_t N = h->N();
+    HIP_TRY(hipSetDevice(h->device));
+    h->macro.ensure(3 * N * sizeof(double));
+    double *m = h->macro.as<double>();
+    if (e.field) {
+        HIP_TRY(hipMemcpyAsync(m, e.field, 3 * N * sizeof(double), hipMemcpyHostToDevice,
+                               h->stream));
+    } else {
+        macro_dispatch(h);
+    }
+    ensure_pinned(h, 64 * sizeof(double));
+    // candidate lists: 2 x (u64 key, u64 hash, i32 idx) per entry
+    if (h->cand_cap == 0) h->cand_cap = initial_cand_cap(N);
+    const int64_t cap = h->cand_cap;
+    h->cand.ensure((size_t)cap * 2 * (2 * sizeof(uint64_t) + sizeof(int32_t)));
+    uint64_t *kf = h->cand.as<uint64_t>();
+    unsigned long long *counters = exchange_counters(h);
+    // counters[0..3] and the error flag (counters + 4) in one fill
+    HIP_TRY(hipMemsetAsync(counters, 0, 5 * sizeof(unsigned long long), h->stream));
+    KeysArgs ka;
+    ka.types = h->types.as<uint8_t>();
+    ka.rho = m;
+    ka.ux = m + N;
+    ka.uy = m + 2 * N;
+    ka.nx = h->nx;
+    ka.ny = h->ny;
+    ka.band_x = e.p.band_x;
+    ka.band_y = e.p.band_y;
+    ka.criterion = e.p.criterion;
+    ka.seed = e.p.seed;
+    ka.cap = cap;
+    ka.count_f = counters;
+    ka.count_s = counters + 1;
+    ka.error = exchange_error(h);
+    ka.kf = kf;
+    ka.hf = kf + cap;
+    ka.ks = kf + 2 * cap;
+    ka.hs = kf + 3 * cap;
+    ka.if_ = reinterpret_cast<int32_t *>(kf + 4 * cap);
+    ka.is = ka.if_ + cap;
+    HIP_TRY(launch_keys(ka, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->pinned, counters, 5 * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, h->stream));
+}
+
+// After the wait: the candidate counts.  False when a list outgrew its
+// capacity (the capacity is then raised; phase 1 must run again).
+bool exchange_counts(Exchange &e) {
+    lbm_handle *h = e.h;
+    const unsigned long long *pc = reinterpret_cast<unsigned long long *>(h->pinned);
+    e.cnt[0] = pc[0];
+    e.cnt[1] = pc[1];
+    if (*reinterpret_cast<const int *>(pc + 4) != 0) {
+        e.status = fail(LBM_EINVAL, "NaN or negative exchange key");
+        return true;
+    }
+    const int64_t need = (int64_t)std::max(e.cnt[0], e.cnt[1]);
+    if (need <= h->cand_cap) return true;
+    h->cand_cap = need;  // grow and recompute
+    h->cand.reset();
+    return false;
+}
+
+// Phase 2: selection, flips, re-initialisation of the flipped cells; the
+// selections, removed densities and the error flag are copied to the pinned
+// staging.  No wait.
+void exchange_select(Exchange &e) {
+    lbm_handle *h = e.h;
+    const int64_t cap = h->cand_cap;
+    uint64_t *kf = h->cand.as<uint64_t>();
+    uint64_t *hf = kf + cap, *ks = kf + 2 * cap, *hs = kf + 3 * cap;
+    int32_t *if_ = reinterpret_cast<int32_t *>(kf + 4 * cap), *is = if_ + cap;
+    e.nf = h->n_fluid;
+    int64_t K = (int64_t)std::floor(e.p.frac * (double)e.nf);
+    if (K < 1) K = 1;
+    e.keff = std::min<int64_t>(K, std::min<int64_t>(e.cnt[0], e.cnt[1]));
+    e.r->n_cand_fluid = (int64_t)e.cnt[0];
+    e.r->n_cand_solid = (int64_t)e.cnt[1];
+    e.r->n_fluid_before = e.nf;
+    const int64_t keff = e.keff;
+    if (keff <= 0) return;
+    // sel: the removed cells' densities, then the removed and the added cell
+    // lists (the layout the pinned readback mirrors)
+    h->sel.ensure((size_t)keff * (sizeof(double) + 2 * sizeof(int32_t)));
+    double *rrho = h->sel.as<double>();
+    int32_t *srem = reinterpret_cast<int32_t *>(rrho + keff), *sadd = srem + keff;
+    h->select_tmp.ensure(select_scratch_bytes(keff));
+    int *err = exchange_error(h);
+    HIP_TRY(launch_select_pair(kf, hf, if_, (int64_t)e.cnt[0], ks, hs, is, (int64_t)e.cnt[1], keff,
+                               srem, sadd, h->select_tmp.p, keff, err, h->stream));
+    HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, rrho,
+                        h->macro.as<double>(), h->stream));
+    if (e.p.reinit == LBM_WARM)  // removed and added cells, adjacent in sel
+        with_storage(h->precision,
+                     [&](auto t) { zero_cells<decltype(t)>(h, srem, 2 * (int)keff); });
+    // the selections and removed densities, then the error flag the
+    // selection kernels may have set
+    const size_t rb = (size_t)keff * (sizeof(double) + 2 * sizeof(int32_t));
+    e.rb_al = (rb + 7) / 8 * 8;
+    ensure_pinned(h, e.rb_al + sizeof(double));
+    HIP_TRY(hipMemcpyAsync(h->pinned, rrho, rb, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char *>(h->pinned) + e.rb_al, err, sizeof(int),
+                           hipMemcpyDeviceToHost, h->stream));
+}
+
+// After the wait: the removed mass in selection order, the whole-lattice
+// reset (COLD), the wall links, and the constant-volume check on the host
+// mirror as the flips apply (every removed cell must have been fluid and
+// every added one solid, each listed once).
+void exchange_finish(Exchange &e) {
+    lbm_handle *h = e.h;
+    const int64_t keff = e.keff, nf = e.nf;
+    std::vector<int32_t> rem(std::max<int64_t>(keff, 0)), add(std::max<int64_t>(keff, 0));
+    double mass_removed = 0.0;
+    if (keff > 0) {
+        if (*reinterpret_cast<const int *>(reinterpret_cast<const char *>(h->pinned) + e.rb_al)) {
+            e.status = fail(LBM_EHIP, "the selection kernels found an inconsistent candidate list");
+            return;
+        }
+        const double *rr = h->pinned;
+        const int32_t *ix = reinterpret_cast<const int32_t *>(h->pinned + keff);
+        std::memcpy(rem.data(), ix, keff * sizeof(int32_t));
+        std::memcpy(add.data(), ix + keff, keff * sizeof(int32_t));
+        for (int64_t k = 0; k < keff; ++k) mass_removed += rr[k];  // selection order
+    }
+    if (e.p.reinit == LBM_COLD) {
+        with_storage(h->precision, [&](auto t) { reset_all<decltype(t)>(h); });
+    }
+    // the wall links around the flipped cells (removed then added, adjacent
+    // in the selection buffer)
+    if (keff > 0) {
+        const int32_t *flipped = reinterpret_cast<const int32_t *>(h->sel.as<double>() + keff);
+        HIP_TRY(launch_build_cells_at(h->types.as<uint8_t>(), h->cell.as<uint16_t>(), flipped,
+                                      (int)(2 * keff), h->nx, h->ny, h->pitch, h->flags,
+                                      h->stream));
+    }
+    int64_t nf_after = nf;
+    for (int64_t k = 0; k < keff; ++k) {
+        uint8_t &tr = h->host_types[rem[k]];
+        nf_after -= tr == LBM_FLUID ? 1 : 0;
+        tr = tr == LBM_FLUID ? (uint8_t)LBM_SOLID : (uint8_t)0xff;
+    }
+    for (int64_t k = 0; k < keff; ++k) {
+        uint8_t &ta = h->host_types[add[k]];
+        nf_after += ta == LBM_SOLID ? 1 : 0;
+        ta = ta == LBM_SOLID ? (uint8_t)LBM_FLUID : (uint8_t)0xff;
+    }
+    for (int64_t k = 0; k < keff; ++k)
+        if (h->host_types[rem[k]] == 0xff || h->host_types[add[k]] == 0xff) nf_after = -1;
+    h->last_removed.assign(rem.begin(), rem.end());
+    h->last_added.assign(add.begin(), add.end());
+    if (keff > 0) {
+        tilings_flip(h, rem, add);
+        rebuild_tiles(h);
+        refit_shape(h);
+        ++h->mask_version;
+    }
+    e.r->k_eff = (int32_t)keff;
+    e.r->n_fluid_after = nf_after;
+    e.r->mass_removed = mass_removed;
+    e.r->mass_added = (double)keff;
+    if (nf_after != nf) e.status = fail(LBM_EHIP, "fluid volume changed by the exchange step");
+}
+
+// Run one phase on every exchange still going; a HIP or allocation failure
+// ends that exchange only.
+template <typename F>
+void exchange_phase(std::vector<Exchange> &ex, F &&f) {
+    for (Exchange &e : ex) {
+        if (e.status != LBM_OK) continue;
+        try {
+            f(e);
+        } catch (const HipFail &x) {
+            e.status = guard_hip(x);
+        } catch (const std::bad_alloc &) {
+            e.status = fail(LBM_ENOMEM, "device allocation failed");
+        }
+    }
+}
+
+// Wait for the streams of the exchanges still going (each stream once).
+void exchange_wait(std::vector<Exchange> &ex) {
+    std::vector<hipStream_t> done;
+    for (Exchange &e : ex) {
+        if (e.status != LBM_OK) continue;
+        if (std::find(done.begin(), done.end(), e.h->stream) != done.end()) continue;
+        const hipError_t err = hipStreamSynchronize(e.h->stream);
+        if (err != hipSuccess) {
+            for (Exchange &o : ex)
+                if (o.status == LBM_OK && o.h->stream == e.h->stream)
+                    o.status = guard_hip(HipFail{err, "hipStreamSynchronize"});
+        }
+        done.push_back(e.h->stream);
+    }
+}
+
+// Exchange steps on many handles, phase by phase: two waits in all (plus one
+// per handle whose candidate list outgrew its capacity).
+void exchange_all(std::vector<Exchange> &ex) {
+    exchange_phase(ex, [](Exchange &e) { exchange_keys(e); });
+    exchange_wait(ex);
+    for (Exchange &e : ex) {
+        if (e.status != LBM_OK || exchange_counts(e)) continue;
+        // a list outgrew its capacity (now raised): recompute once
+        std::vector<Exchange> one(1, e);
+        exchange_phase(one, [](Exchange &x) { exchange_keys(x); });
+        exchange_wait(one);
+        e.status = one[0].status;
+        if (e.status == LBM_OK && !exchange_counts(e))
+            e.status = fail(LBM_EHIP, "candidate count changed between passes");
+    }
+    exchange_phase(ex, [](Exchange &e) { exchange_select(e); });
+    exchange_wait(ex);
+    exchange_phase(ex, [](Exchange &e) { exchange_finish(e); });
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_shape_update(lbm_handle *h, const lbm_shape_params *p,
+                     const double *rho_ux_uy, lbm_shape_result *r) {
+    g_error.clear();
+    const int rc = exchange_check(h, p, r);
+    if (rc != LBM_OK) return rc;
+    std::memset(r, 0, sizeof *r);
+    std::vector<Exchange> ex(1);
+    ex[0].h = h;
+    ex[0].p = *p;
+    ex[0].field = rho_ux_uy;
+    ex[0].r = r;
+    exchange_all(ex);
+    if (ex[0].status != LBM_OK) return ex[0].status;
+    return LBM_OK;
+}
+
+int lbm_shape_update_many(lbm_handle *const *hs, const lbm_shape_params *ps, int32_t n,
+                          lbm_shape_result *rs, int32_t *status) {
+    g_error.clear();
+    if (n < 0 || (n > 0 && (!hs || !ps || !rs || !status)))
+        return fail(LBM_EINVAL, "null array or negative count");
+    std::vector<Exchange> ex(n);
+    int worst = LBM_OK;
+    for (int32_t k = 0; k < n; ++k) {
+        for (int32_t j = 0; j < k; ++j)
+            if (hs[j] == hs[k]) return fail(LBM_EINVAL, "a handle is listed twice");
+        status[k] = exchange_check(hs[k], &ps[k], &rs[k]);
+        if (status[k] == LBM_OK) std::memset(&rs[k], 0, sizeof rs[k]);
+        ex[k].h = hs[k];
+        ex[k].p = ps[k];
+        ex[k].r = &rs[k];
+        ex[k].status = status[k];
+    }
+    exchange_all(ex);
+    for (int32_t k = 0; k < n; ++k) {
+        status[k] = ex[k].status;
+        if (status[k] < worst) worst = status[k];
+    }
+    return worst;
 }
 
 int lbm_last_exchange(lbm_handle *h, int64_t *removed, int64_t *added,

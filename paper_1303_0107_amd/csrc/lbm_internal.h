@@ -241,6 +241,11 @@ hipError_t launch_boundary(const MacroArgs<T> &a, const int32_t *y0,
                            hipStream_t s);
 hipError_t launch_build_cells(const uint8_t *types, uint16_t *cell, int nx,
                               int ny, int pitch, int flags, hipStream_t s);
+// The cell words of the 3 x 3 neighbourhoods of `count` listed cells (logical
+// indices; device array), after those cells changed type.
+hipError_t launch_build_cells_at(const uint8_t *types, uint16_t *cell, const int32_t *cells,
+                                 int count, int nx, int ny, int pitch, int flags,
+                                 hipStream_t s);
 // Put the given cells (logical indices) / the whole buffer at rest
 // (f_i = w_i: offsets 0 in single precision, w_i in double precision).
 template <typename T>

@@ -397,8 +397,34 @@ __global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<T> a, const int3
 }
 
 // ---------------------------------------------------------------------------
-// Cell words from the logical type map: wall bit of population i set when
-// the pull source x - c_i is solid or off the lattice.  Pad columns are solid.
+// Cell word of cell (x, y) from the logical type map: wall bit of population
+// i set when the pull source x - c_i is solid or off the lattice.
+__device__ __forceinline__ uint32_t cell_word(const uint8_t *types, int x, int y, int nx, int ny,
+                                              int flags) {
+    const uint32_t t = types[(size_t)y * nx + x];
+    uint32_t w = t << 8;
+    if (t != kSolid) {
+        const bool sym = (flags & kFlagSymmetryTop) != 0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            // a source beyond the symmetry line is its mirror in row ny-1
+            const int sx = x - kCx[i];
+            int sy = y - kCy[i];
+            if (sym && sy == ny) sy = ny - 1;
+            const bool wall = sx < 0 || sx >= nx || sy < 0 || sy >= ny ||
+                              types[(size_t)sy * nx + sx] == kSolid;
+            w |= (wall ? 1u : 0u) << (i - 1);
+        }
+        if ((flags & kFlagNeumannOutlet) && t == kOutlet) {
+            w |= kWordNeumann;
+            if (x > 0 && types[(size_t)y * nx + x - 1] != kSolid) w |= kWordLeftLive;
+        }
+        if (sym && y == ny - 1) w |= kWordGeneral;
+    }
+    return w;
+}
+
+// Cell words of the whole lattice.  Pad columns are solid.
 __global__ __launch_bounds__(256) void build_cells_kernel(const uint8_t *types,
                                                           uint16_t *cell,
                                                           int nx, int ny,
@@ -406,30 +432,25 @@ __global__ __launch_bounds__(256) void build_cells_kernel(const uint8_t *types,
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
     if (x >= pitch || y >= ny) return;
-    uint32_t w = 0;
-    if (x < nx) {
-        const uint32_t t = types[(size_t)y * nx + x];
-        w = t << 8;
-        if (t != kSolid) {
-            const bool sym = (flags & kFlagSymmetryTop) != 0;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                // a source beyond the symmetry line is its mirror in row ny-1
-                const int sx = x - kCx[i];
-                int sy = y - kCy[i];
-                if (sym && sy == ny) sy = ny - 1;
-                const bool wall = sx < 0 || sx >= nx || sy < 0 || sy >= ny ||
-                                  types[(size_t)sy * nx + sx] == kSolid;
-                w |= (wall ? 1u : 0u) << (i - 1);
-            }
-            if ((flags & kFlagNeumannOutlet) && t == kOutlet) {
-                w |= kWordNeumann;
-                if (x > 0 && types[(size_t)y * nx + x - 1] != kSolid) w |= kWordLeftLive;
-            }
-            if (sym && y == ny - 1) w |= kWordGeneral;
-        }
-    }
+    const uint32_t w = x < nx ? cell_word(types, x, y, nx, ny, flags) : 0u;
     cell[(size_t)y * pitch + x] = (uint16_t)w;
+}
+
+// Cell words of the 3 x 3 neighbourhood of each listed cell (logical
+// indices): after cells flipped, the only words that change are those of the
+// flipped cells and of their eight neighbours (a cell's word depends on its
+// own type and those of its eight neighbours).  Nine threads per listed cell;
+// a word reached from two listed cells is written twice with the same value.
+__global__ __launch_bounds__(256) void build_cells_at_kernel(const uint8_t *types, uint16_t *cell,
+                                                             const int32_t *cells, int count,
+                                                             int nx, int ny, int pitch,
+                                                             int flags) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 9 * count) return;
+    const int l = cells[t / 9], j = t % 9;
+    const int x = l % nx + (j % 3) - 1, y = l / nx + (j / 3) - 1;
+    if (x < 0 || x >= nx || y < 0 || y >= ny) return;
+    cell[(size_t)y * pitch + x] = (uint16_t)cell_word(types, x, y, nx, ny, flags);
 }
 
 // Every population offset of the given cells to zero: the rest equilibrium
@@ -498,10 +519,13 @@ __device__ __forceinline__ uint64_t key_bits(double k) {
 // Candidate keys of the interface cells inside the band.  Fluid candidates
 // sort ascending on (key, hash, idx); solid candidates descending on key,
 // which is stored complemented so that both lists sort ascending.
-__global__ __launch_bounds__(256) void keys_kernel(KeysArgs a) {
+// Blocks of 64 x 16 cells (16 waves, one row each): the candidates' list
+// slots are claimed with one atomic per block and list.
+constexpr int kKeysRows = 16;
+__global__ __launch_bounds__(64 * kKeysRows) void keys_kernel(KeysArgs a) {
 #pragma clang fp contract(off)
     const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int y = blockIdx.y * kKeysRows + threadIdx.y;
     const int nx = a.nx;
     const bool in_band = x >= a.band_x && x <= a.nx - 1 - a.band_x && y >= a.band_y &&
                          y <= a.ny - 1 - a.band_y;
@@ -544,18 +568,31 @@ __global__ __launch_bounds__(256) void keys_kernel(KeysArgs a) {
     if (touch && !(key >= 0.0)) bad = true;
     if (bad) atomicOr(a.error, 1);
     const bool is_f = touch && !bad && t == kFluid, is_s = touch && !bad && t == kSolid;
-    // One counter update per wave and list (each row of the block is a wave):
-    // lane k of the wave takes slot base + (candidates below lane k).
-    const int lane = threadIdx.x;
+    // One counter update per block and list: each wave (a row of the block)
+    // counts its candidates, thread 0 claims the block's slots, and lane k of
+    // wave w takes slot base + (candidates of waves < w) + (candidates of the
+    // wave below lane k).
+    __shared__ unsigned wave_n[2][kKeysRows];
+    __shared__ unsigned long long block_base[2];
+    const int lane = threadIdx.x, w = threadIdx.y;
     const uint64_t below = (1ull << lane) - 1ull;
     const uint64_t mf = __ballot(is_f), ms = __ballot(is_s);
-    unsigned long long bf = 0, bs = 0;
     if (lane == 0) {
-        if (mf) bf = atomicAdd(a.count_f, (unsigned long long)__popcll(mf));
-        if (ms) bs = atomicAdd(a.count_s, (unsigned long long)__popcll(ms));
+        wave_n[0][w] = (unsigned)__popcll(mf);
+        wave_n[1][w] = (unsigned)__popcll(ms);
     }
-    bf = __shfl(bf, 0, 64);
-    bs = __shfl(bs, 0, 64);
+    __syncthreads();
+    if (w == 0 && lane < 2) {
+        unsigned long long tot = 0;
+        for (int k = 0; k < kKeysRows; ++k) tot += wave_n[lane][k];
+        block_base[lane] = tot ? atomicAdd(lane == 0 ? a.count_f : a.count_s, tot) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long bf = block_base[0], bs = block_base[1];
+    for (int k = 0; k < w; ++k) {
+        bf += wave_n[0][k];
+        bs += wave_n[1][k];
+    }
     if (!is_f && !is_s) return;
     const uint64_t kb = key_bits(key);
     const uint64_t h = splitmix64(a.seed + (uint64_t)l);
@@ -679,6 +716,16 @@ hipError_t launch_build_cells(const uint8_t *types, uint16_t *cell, int nx,
     return hipGetLastError();
 }
 
+hipError_t launch_build_cells_at(const uint8_t *types, uint16_t *cell, const int32_t *cells,
+                                 int count, int nx, int ny, int pitch, int flags,
+                                 hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t threads = 9 * (int64_t)count;
+    hipLaunchKernelGGL(build_cells_at_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256),
+                       0, s, types, cell, cells, count, nx, ny, pitch, flags);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t rest_cells_impl(T *f, size_t plane, const int32_t *cells, int count, int nx,
                            int pitch, hipStream_t s) {
@@ -732,8 +779,9 @@ hipError_t launch_import_plane(T *f, const uint16_t *cell, const double *in,
 }
 
 hipError_t launch_keys(const KeysArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(keys_kernel, grid_cells(a.nx, a.ny), dim3(64, 4), 0, s,
-                       a);
+    hipLaunchKernelGGL(keys_kernel,
+                       dim3((unsigned)((a.nx + 63) / 64), (unsigned)((a.ny + kKeysRows - 1) / kKeysRows)),
+                       dim3(64, kKeysRows), 0, s, a);
     return hipGetLastError();
 }
 

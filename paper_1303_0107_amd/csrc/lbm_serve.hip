@@ -113,26 +113,49 @@ struct lbm_server {
         cv_done.notify_all();
     }
 
-    // Take every event a session has reached; returns false once it is done.
-    bool take_events(Session &s) {
-        while (s.status == LBM_OK && s.to_go == 0) {
-            if (s.req.kind == LBM_REQ_OPTIMIZE && s.iter < s.req.iterations) {
-                lbm_shape_params p = s.req.shape;
-                p.seed = s.req.shape.seed + (uint64_t)s.iter;
-                lbm_shape_result r{};
-                const int rc = lbm_shape_update(s.h, &p, nullptr, &r);
-                if (rc != LBM_OK) {
-                    s.status = rc;
-                    break;
+    // Take the exchange steps the given sessions have reached, all due ones
+    // in one lbm_shape_update_many call (repeated while an iteration of zero
+    // steps leaves a session due again).  A session is done once it is due
+    // with no iteration left, or failed.
+    void take_events(std::vector<Session *> &ss) {
+        for (;;) {
+            std::vector<Session *> due;
+            for (Session *s : ss)
+                if (s->status == LBM_OK && s->to_go == 0 && s->req.kind == LBM_REQ_OPTIMIZE &&
+                    s->iter < s->req.iterations)
+                    due.push_back(s);
+            if (due.empty()) return;
+            std::vector<lbm_handle *> hs;
+            std::vector<lbm_shape_params> ps;
+            for (Session *s : due) {
+                lbm_shape_params p = s->req.shape;
+                p.seed = s->req.shape.seed + (uint64_t)s->iter;
+                hs.push_back(s->h);
+                ps.push_back(p);
+            }
+            std::vector<lbm_shape_result> rs(due.size());
+            std::vector<int32_t> st(due.size(), LBM_OK);
+            const double t0 = now_seconds();
+            (void)lbm_shape_update_many(hs.data(), ps.data(), (int32_t)due.size(), rs.data(),
+                                        st.data());
+            {
+                std::lock_guard<std::mutex> g(mu);
+                this->st.exchange_seconds += now_seconds() - t0;
+                this->st.exchanges += (int64_t)due.size();
+                ++this->st.exchange_calls;
+            }
+            for (size_t k = 0; k < due.size(); ++k) {
+                Session *s = due[k];
+                if (st[k] != LBM_OK) {
+                    s->status = st[k];
+                    continue;
                 }
-                ++s.iter;
-                s.to_go = s.req.steps_per_iteration;
-            } else {
-                return false;
+                ++s->iter;
+                s->to_go = s->req.steps_per_iteration;
             }
         }
-        return s.status == LBM_OK;
     }
+    static bool still_going(const Session &s) { return s.status == LBM_OK && s.to_go > 0; }
 
     void drop_group(int precision) {
         auto it = groups.find(precision);
@@ -155,7 +178,9 @@ struct lbm_server {
                 continue;
             }
             s.to_go = s.req.solve_steps;
-            if (!take_events(s)) {
+            std::vector<Session *> one{&s};
+            take_events(one);
+            if (!still_going(s)) {
                 complete(s);
                 continue;
             }
@@ -224,8 +249,7 @@ struct lbm_server {
         }
         const double t1 = now_seconds();
         int64_t cells = 0;
-        std::vector<Session> still;
-        std::vector<Session> finished;
+        std::vector<Session *> all;
         for (Session &s : active) {
             auto f = failed.find(s.req.geom.precision);
             if (f != failed.end()) {
@@ -235,11 +259,12 @@ struct lbm_server {
                 s.steps += q;
                 cells += (int64_t)s.req.geom.nx * s.req.geom.ny;
             }
-            if (s.status == LBM_OK && take_events(s))
-                still.push_back(s);
-            else
-                finished.push_back(s);
+            all.push_back(&s);
         }
+        take_events(all);
+        std::vector<Session> still;
+        std::vector<Session> finished;
+        for (Session &s : active) (still_going(s) ? still : finished).push_back(s);
         // batches hold the handles: drop the affected ones before releasing
         for (const Session &s : finished) drop_group(s.req.geom.precision);
         for (Session &s : finished) complete(s);

@@ -93,7 +93,8 @@ class lbm_server_stats(ctypes.Structure):
                 ("cell_steps", ctypes.c_int64), ("nonsolid_cell_steps", ctypes.c_int64),
                 ("busy_seconds", ctypes.c_double), ("admit_seconds", ctypes.c_double),
                 ("sweep_seconds", ctypes.c_double), ("event_seconds", ctypes.c_double),
-                ("peak_bytes", ctypes.c_size_t)]
+                ("peak_bytes", ctypes.c_size_t), ("exchange_seconds", ctypes.c_double),
+                ("exchanges", ctypes.c_int64), ("exchange_calls", ctypes.c_int64)]
 
 
 _lib = None
@@ -153,6 +154,7 @@ def load() -> ctypes.CDLL:
         "lbm_precision_info": (ctypes.c_int, [i32, P, P]),
         "lbm_outlet_stats_noalloc": (ctypes.c_int, [H, P, i32, P]),
         "lbm_get_tb_variant": (ctypes.c_int, [H, P]),
+        "lbm_shape_update_many": (ctypes.c_int, [P, P, i32, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -253,6 +255,19 @@ def lbm_shape_update(h, params: lbm_shape_params, rho_ux_uy=None):
         ptr = _p(arr)
     _check(lib.lbm_shape_update(h, ctypes.byref(params), ptr, ctypes.byref(r)))
     return r
+
+
+def lbm_shape_update_many(handles, params):
+    """Exchange steps on many handles at once; returns (results, statuses)."""
+    n = len(handles)
+    hs = (ctypes.c_void_p * max(n, 1))(*handles)
+    ps = (lbm_shape_params * max(n, 1))(*params)
+    rs = (lbm_shape_result * max(n, 1))()
+    st = (ctypes.c_int32 * max(n, 1))()
+    rc = load().lbm_shape_update_many(hs, ps, n, rs, st)
+    if rc < 0 and all(st[k] >= 0 for k in range(n)):
+        _check(rc)
+    return [rs[k] for k in range(n)], [st[k] for k in range(n)]
 
 
 def lbm_last_exchange(h, cap: int):

@@ -17,6 +17,7 @@ EXPECTED = {
     "lbm_batch_set_graphs", "lbm_state_digest", "lbm_server_create", "lbm_server_submit",
     "lbm_server_poll", "lbm_server_drain", "lbm_server_stats_get", "lbm_server_destroy",
     "lbm_precision_info", "lbm_outlet_stats_noalloc", "lbm_get_tb_variant",
+    "lbm_shape_update_many",
 }
 
 
@@ -45,7 +46,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(lbm.lbm_server_config) == 8 + 16
     assert ctypes.sizeof(lbm.lbm_request) == ctypes.sizeof(lbm.lbm_geometry_desc) + 8 + 16 + 32
     assert ctypes.sizeof(lbm.lbm_result) == 8 + 8 + 8 + 8 + 8 + 24 + ctypes.sizeof(lbm.lbm_stats)
-    assert ctypes.sizeof(lbm.lbm_server_stats) == 8 * 8 + 4 * 8 + 8
+    assert ctypes.sizeof(lbm.lbm_server_stats) == 8 * 8 + 4 * 8 + 8 + 3 * 8
     assert ctypes.sizeof(lbm.lbm_shape_result) == 8 + 32 + 16
 
 

@@ -472,6 +472,37 @@ def test_exchange_bit_exact_many_candidates(frac, quant):
     assert r.mass_removed == ro.mass_removed
 
 
+def test_exchange_on_many_handles_equals_one_at_a_time():
+    """lbm_shape_update_many gives each handle exactly the result, mask and
+    state lbm_shape_update gives it alone; the FP64 member is also checked
+    against the oracle."""
+    cands = I.batch_candidates(count=3, seed=31)
+    precs = [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F32_S_F16]
+    many = [lbm.Lattice(c.types(), c.tau, c.u_peak, precision=p) for c, p in zip(cands, precs)]
+    alone = [lbm.Lattice(c.types(), c.tau, c.u_peak, precision=p) for c, p in zip(cands, precs)]
+    o = oracle.Lattice(cands[0].types(), cands[0].tau, cands[0].u_peak)
+    for g in many + alone:
+        g.run(400, 0.0, 100)
+    o.run(400, 0.0, 100)
+    params = [lbm.make_shape_params(frac=0.02, seed=11 + k) for k in range(3)]
+    rs, st = lbm.lbm_shape_update_many([g.h for g in many], params)
+    assert st == [0, 0, 0]
+    for k, (g, a) in enumerate(zip(many, alone)):
+        ra = lbm.lbm_shape_update(a.h, params[k])
+        assert (rs[k].k_eff, rs[k].n_cand_fluid, rs[k].n_cand_solid, rs[k].mass_removed) == \
+            (ra.k_eff, ra.n_cand_fluid, ra.n_cand_solid, ra.mass_removed)
+        assert np.array_equal(g.mask(), a.mask()) and np.array_equal(g.state(), a.state())
+    ro = o.shape_update(frac=0.02, seed=11)
+    assert np.array_equal(many[0].mask(), o.types) and rs[0].mass_removed == ro.mass_removed
+    # after the exchange, the handles run on as before
+    for g, a in zip(many, alone):
+        g.run(100, 0.0, 100)
+        a.run(100, 0.0, 100)
+        assert np.array_equal(g.state(), a.state())
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_shape_update_many([many[0].h, many[0].h], params[:2])
+
+
 @pytest.mark.parametrize("reinit", [lbm.LBM_WARM, lbm.LBM_COLD])
 def test_reinitialisation_matches_oracle(reinit):
     wl = I.CORRECTNESS_128x64
