@@ -54,25 +54,32 @@ HBM_PEAK_GBS = 8000.0
 # reads and writes u_prev (two FP64 planes, 32 B per non-solid cell), so the
 # reported traffic per launch is full + 32 B * N_ns / (launches per interval).
 MEASURED_TRAFFIC_PER_FULL_LAUNCH = {
-    # shape 5 (32x64 dense regions, 9 steps per launch), 236 active tiles
-    ("distributor-1024x512-L3", "f32", 5): 8.490e6,
-    # shape 1 (32x64 dense regions, 8 steps per launch), 234 active tiles
-    ("distributor-1024x512-L3", "f32", 1): 8.420e6,
-    # shape 0 (32x64 compacted regions)
-    ("distributor-1024x512-L3", "f32", 0): 8.479e6,
+    # profiles/sweep_tb_float_distributor-1024x512.txt: shape 5 (32x64 dense
+    # regions, 9 steps per launch, 236 active tiles), shape 1 (32x64 dense, 8
+    # steps per launch, 234 tiles), shape 0 (32x64 compacted)
+    ("distributor-1024x512-L3", "f32", 5): 8.473e6,
+    ("distributor-1024x512-L3", "f32", 1): 8.417e6,
+    ("distributor-1024x512-L3", "f32", 0): 8.474e6,
     # profiles/sweep_tb_double_distributor-1024x512.txt: shape 3 (32x64 in
     # place, 8 steps per launch), shape 0 (16x64 compacted, 4 steps per
     # launch), shape 1 (16x64 dense)
-    ("distributor-1024x512-L3", "f64", 3): 18.724e6,
-    ("distributor-1024x512-L3", "f64", 0): 13.140e6,
-    ("distributor-1024x512-L3", "f64", 1): 13.135e6,
+    ("distributor-1024x512-L3", "f64", 3): 18.722e6,
+    ("distributor-1024x512-L3", "f64", 0): 13.145e6,
+    ("distributor-1024x512-L3", "f64", 1): 13.133e6,
     # profiles/sweep_tb_float_channel-1024x512.txt: shape 4 (16x64 dense, 4
     # steps per launch), shape 3 (16x64 compacted), shapes 1 and 0 (32x64
-    # dense and compacted, 8 steps per launch)
-    ("channel-1024x512", "f32", 4): 41.019e6,
-    ("channel-1024x512", "f32", 3): 41.042e6,
-    ("channel-1024x512", "f32", 1): 43.187e6,
-    ("channel-1024x512", "f32", 0): 43.255e6,
+    # dense and compacted, 8 steps per launch), shape 5 (32x64 dense, 9 steps)
+    ("channel-1024x512", "f32", 4): 41.018e6,
+    ("channel-1024x512", "f32", 3): 41.052e6,
+    ("channel-1024x512", "f32", 1): 43.500e6,
+    ("channel-1024x512", "f32", 0): 43.671e6,
+    ("channel-1024x512", "f32", 5): 44.356e6,
+    # profiles/sweep_tb_float_channel-4096x2048.txt, the same shapes
+    ("channel-4096x2048", "f32", 4): 636.576e6,
+    ("channel-4096x2048", "f32", 3): 639.227e6,
+    ("channel-4096x2048", "f32", 1): 935.988e6,
+    ("channel-4096x2048", "f32", 0): 936.232e6,
+    ("channel-4096x2048", "f32", 5): 1027.038e6,
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
@@ -81,20 +88,20 @@ MEASURED_TRAFFIC_PER_LAUNCH = {
     # blocking (0: 32x64 compacted, 1: 32x64 dense, 2: 32x64 compacted with
     # 4 steps per launch, 3: 16x64 compacted, 4: 16x64 dense, 5: 32x64 dense
     # with 9 steps per launch), 6 = one step per launch
-    ("batch-256-candidates", "f32", 4, 1): 700.885e6,
-    ("batch-256-candidates", "f32", 4, 0): 1366.056e6,
-    ("batch-256-candidates", "f32", 3, 1): 700.902e6,
-    ("batch-256-candidates", "f32", 3, 0): 1366.076e6,
-    ("batch-256-candidates", "f32", 2, 1): 708.338e6,
-    ("batch-256-candidates", "f32", 2, 0): 1090.860e6,
-    ("batch-256-candidates", "f32", 1, 1): 709.156e6,
-    ("batch-256-candidates", "f32", 1, 0): 1556.346e6,
-    ("batch-256-candidates", "f32", 0, 1): 709.214e6,
-    ("batch-256-candidates", "f32", 0, 0): 1556.404e6,
-    ("batch-256-candidates", "f32", 5, 1): 708.558e6,
-    ("batch-256-candidates", "f32", 5, 0): 1637.078e6,
-    ("batch-256-candidates", "f32", 6, 1): 684.539e6,
-    ("batch-256-candidates", "f32", 6, 0): 775.523e6,
+    ("batch-256-candidates", "f32", 4, 1): 700.888e6,
+    ("batch-256-candidates", "f32", 4, 0): 1366.060e6,
+    ("batch-256-candidates", "f32", 3, 1): 700.889e6,
+    ("batch-256-candidates", "f32", 3, 0): 1366.067e6,
+    ("batch-256-candidates", "f32", 2, 1): 708.367e6,
+    ("batch-256-candidates", "f32", 2, 0): 1090.893e6,
+    ("batch-256-candidates", "f32", 1, 1): 709.166e6,
+    ("batch-256-candidates", "f32", 1, 0): 1556.355e6,
+    ("batch-256-candidates", "f32", 0, 1): 709.218e6,
+    ("batch-256-candidates", "f32", 0, 0): 1556.434e6,
+    ("batch-256-candidates", "f32", 5, 1): 708.554e6,
+    ("batch-256-candidates", "f32", 5, 0): 1637.069e6,
+    ("batch-256-candidates", "f32", 6, 1): 684.541e6,
+    ("batch-256-candidates", "f32", 6, 0): 775.526e6,
 }
 
 
@@ -430,12 +437,20 @@ def bench_serve(args) -> int:
 
 
 # Vector ALU instructions (wave instructions, rocprofv3 SQ_INSTS_VALU) of one
-# full launch of the blocked sweep, keyed like the traffic table;
-# profiles/sweep_tb_*_counters.txt.  Each wave instruction occupies a SIMD
-# for 4 cycles (64 lanes on 16-wide SIMDs; packed FP32 is not used), so the
-# chip issues at most 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave
-# instructions per second.
-MEASURED_VALU_PER_FULL_LAUNCH = {}
+# full launch of the blocked sweep, keyed like the traffic table, from the
+# same profiles.  Each wave instruction occupies a SIMD for 4 cycles (64
+# lanes on 16-wide SIMDs; packed FP32 is not used), so the chip issues at
+# most 256 CUs x 4 SIMDs x 2.4 GHz / 4 = 614.4 G wave instructions per second.
+MEASURED_VALU_PER_FULL_LAUNCH = {
+    ("distributor-1024x512-L3", "f32", 5): 3.937e6,
+    ("distributor-1024x512-L3", "f32", 1): 3.455e6,
+    ("distributor-1024x512-L3", "f32", 0): 3.218e6,
+    ("channel-1024x512", "f32", 4): 8.107e6,
+    ("channel-1024x512", "f32", 3): 9.306e6,
+    ("channel-1024x512", "f32", 1): 15.07e6,
+    ("channel-1024x512", "f32", 0): 16.11e6,
+    ("channel-1024x512", "f32", 5): 19.17e6,
+}
 VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
 

@@ -19,7 +19,8 @@ SHORT = [("lbm::OffsetCell<float, float, float>", "F32Cell"),
          ("lbm::OffsetCell<float, double, double>", "F32Cell(double arithmetic)"),
          ("lbm::OffsetCell<_Float16, float, float>", "H16Cell"),
          ("lbm::OffsetCell<__hip_bfloat16, float, float>", "BF16Cell"),
-         ("lbm::f64::Cell", "F64Cell"), ("void ", ""), ("lbm::sweep::", ""), ("lbm::", "")]
+         ("lbm::f64::Cell", "F64Cell"), ("void ", ""), ("(anonymous namespace)::", ""),
+         ("lbm::sweep::", ""), ("lbm::", "")]
 
 
 def short(name: str) -> str:
@@ -31,17 +32,31 @@ def short(name: str) -> str:
 
 def per_kernel(path, counter):
     """Mean counter value per (kernel, grid size), dispatch counts, and the
-    largest single value read by the plain copy kernel."""
+    readings of the plain copy kernel in dispatch order."""
     agg = collections.defaultdict(list)
-    copy_max = 0.0
+    copies = []
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] == counter:
             v = float(r["Counter_Value"])
             agg[(r["Kernel_Name"], int(r["Grid_Size"]))].append(v)
             if "copyBuffer" in r["Kernel_Name"]:
-                copy_max = max(copy_max, v)
+                copies.append((int(r["Dispatch_Id"]), v))
+    copies = [v for _, v in sorted(copies)]
     return ({k: sum(v) / len(v) for k, v in agg.items()}, {k: len(v) for k, v in agg.items()},
-            copy_max)
+            copies)
+
+
+def copy_readings(fetch_copies, write_copies, nbytes):
+    """FETCH_SIZE and WRITE_SIZE of the calibration copy of nbytes.  The two
+    runs make the same copies in the same order; WRITE_SIZE of a copy reads
+    the bytes it writes (in KiB), so the calibration copy is the one whose
+    write reading is nbytes / 1024.  Without such a reading (or if the runs
+    made different numbers of copies), the largest copy is taken."""
+    if len(fetch_copies) == len(write_copies):
+        for f, w in zip(fetch_copies, write_copies):
+            if w * 1024.0 == nbytes:
+                return f, w
+    return max(fetch_copies), max(write_copies)
 
 
 def main():
@@ -78,10 +93,9 @@ def main():
         return
     print()
     print(f"counters: {a.pmc_cmd}")
-    # The copy of --copy-bytes is the largest copy the program makes, so it
-    # is the copy dispatch with the largest reading.
-    fetch, nf, copy_f = per_kernel(a.fetch, "FETCH_SIZE")
-    write, nw, copy_w = per_kernel(a.write, "WRITE_SIZE")
+    fetch, nf, copies_f = per_kernel(a.fetch, "FETCH_SIZE")
+    write, nw, copies_w = per_kernel(a.write, "WRITE_SIZE")
+    copy_f, copy_w = copy_readings(copies_f, copies_w, a.copy_bytes)
     kib = 1024.0
     sf = a.copy_bytes / (copy_f * kib)
     sw = a.copy_bytes / (copy_w * kib)
