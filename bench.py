@@ -505,15 +505,22 @@ def optimise_leg(args, w, prec_name: str, copy_gbs: float):
     print(f"# autotune: shape {shape} ({rows} rows, halo {halo}); us/step "
           + " ".join(f"{x * 1e3:.3f}" for x in tune_ms), file=sys.stderr, flush=True)
 
+    ex_ms, stats_ms = [], []
+
     def one_step(seed):
+        t = time.perf_counter()
         r, _, _ = lat.shape_update(frac=frac, seed=seed)
+        ex_ms.append((time.perf_counter() - t) * 1e3)
         rc, n, res = lat.run(args.cap, args.tol, k)
+        t = time.perf_counter()
         flow, st = lat.stats()
+        stats_ms.append((time.perf_counter() - t) * 1e3)
         return n, res, flow, st, r
 
     for i in range(args.warmup):
         one_step(1000 + i)
     torch.cuda.synchronize()
+    del ex_ms[:], stats_ms[:]
     lat.profile_sweeps(True)
     sweeps = 0
     t0 = time.perf_counter()
@@ -580,6 +587,8 @@ def optimise_leg(args, w, prec_name: str, copy_gbs: float):
             "tuned_shape": {"index": shape, "rows": rows, "halo": halo, "tile": [tw, th]},
             "shape_in_use": in_use,
             "tune_us_per_step": [round(x * 1e3, 3) for x in tune_ms],
+            "exchange_ms_median": round(float(np.median(ex_ms)), 3),
+            "stats_ms_median": round(float(np.median(stats_ms)), 3),
         },
         "roofline": roof,
     }

@@ -212,10 +212,36 @@ class Workload:
     def types(self) -> np.ndarray:
         if self.kind == "channel":
             return channel(self.nx, self.ny)
+        if self.kind == "collector-half":
+            return lower_half(collector(self.nx, 2 * self.ny, self.levels, self.widths))
         return distributor(self.nx, self.ny, self.levels, self.widths)
 
 
-# The five workloads the method is exercised on (names describe them).
+def mirror_widths(widths, ny: int) -> list[int]:
+    """Round widths[k] to the nearest integer of the parity that keeps the
+    generator's level-k bars mirror symmetric about the mid line of ny rows:
+    even where ny / 2^(k+1) is an integer (the bar centre sits on a row
+    boundary), odd otherwise (ties go to the smaller width)."""
+    out = []
+    for k, w in enumerate(widths):
+        even = (ny % 2 ** (k + 1)) == 0
+        lo = math.floor(w)
+        if (lo % 2 == 0) != even:
+            lo -= 1
+        out.append(lo if w - lo <= lo + 2 - w else lo + 2)
+    return out
+
+
+def paper_collector_widths(w_in: int = 11, levels: int = 4, ny_full: int = 360) -> list[int]:
+    """Channel widths in cells of the paper's own run (Sec. 3.3): the Eq. 8
+    chain of Table 1 (depth 10 mm, finest channel 2 mm) scaled so that the
+    finest channel is W_in cells (depth 55 cells); the trunk comes out at
+    52.4 cells, the W_out of Sec. 3.3.  Rounded by mirror_widths."""
+    h = 10.0 * w_in / 2.0
+    return mirror_widths(width_law_chain(h, float(w_in), levels), ny_full)
+
+
+# The workloads the method is exercised on (names describe them).
 CORRECTNESS_128x64 = Workload("distributor-128x64-L2", 128, 64, 2, [8, 6, 4], 0.8, 0.05, seed=1,
                               extra={"warm_steps": 5000, "iters": 10, "steps_per_iter": 5000,
                                      "frac": 0.01})
@@ -227,6 +253,16 @@ PRECISION_2048x1024 = Workload("distributor-2048x1024-L4", 2048, 1024, 4, [128, 
                                0.55, 0.03, seed=3, extra={"steps": 20000})
 CHANNEL_4096x2048 = Workload("channel-4096x2048", 4096, 2048, 0, [], 0.6, 0.04, seed=2,
                              kind="channel")
+# The paper's own run (Sec. 3.3): a collector computed on half its domain,
+# 360 x 180 cells (the mirrored full domain 360 x 360, the square footprint of
+# Sec. 3.2's outlets), 2^4 inlets of W_in = 11 cells (8 in the half), one
+# outlet of W_out = 52 (26 rows in the half, against the symmetry line),
+# Neumann outlet, nu = 0.04 (tau = 3 nu + 1/2 = 0.62), mean inlet velocity
+# u_in = 0.08 (a parabola of peak 3/2 u_in), Re_in = 22.
+PAPER_COLLECTOR_360x180 = Workload(
+    "collector-half-360x180", 360, 180, 4, [52, 34, 24, 15, 11], 0.62, 0.12, seed=6,
+    kind="collector-half",
+    extra={"flags": 3, "nu": 0.04, "u_in": 0.08, "w_in": 11, "w_out": 52})
 
 
 def batch_candidates(count: int = 256, seed: int = 4):

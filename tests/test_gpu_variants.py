@@ -125,3 +125,36 @@ def test_batch_with_flagged_members_matches_each_alone():
 def test_unknown_flags_are_refused():
     with pytest.raises(lbm.LbmError):
         lbm.Lattice(I.channel(32, 8), 0.8, 0.02, precision=lbm.LBM_F32, flags=4)
+
+
+def test_paper_case_f64_bit_for_bit_through_the_instability():
+    """The paper's own numbers (Sec. 3.3) on the half-domain collector: the
+    GPU's FP64 path follows the oracle bit for bit while the density climbs,
+    and stops with EUNSTABLE at the same check (step 3500)."""
+    w = I.PAPER_COLLECTOR_360x180
+    t, flags = w.types(), w.extra["flags"]
+    print(f"paper case {w.name} flags {flags}", flush=True)
+    o = oracle.Lattice(t, w.tau, w.u_peak, flags=flags)
+    g = lbm.Lattice(t, w.tau, w.u_peak, precision=lbm.LBM_F64, flags=flags)
+    for _ in range(3):
+        so, no, _ = o.run(1000, 0.0, 100)
+        sg, ng, _ = g.run(1000, 0.0, 100)
+        assert (sg, ng) == (so, no) == (lbm.LBM_OK, 1000)
+        assert np.array_equal(g.state().reshape(o.fs.shape), o.fs)
+    so, no, _ = o.run(5000, 0.0, 100)
+    sg, ng, _ = g.run(5000, 0.0, 100)
+    assert so == oracle.EUNSTABLE and sg == lbm.LBM_EUNSTABLE
+    assert ng == no == 500
+    g.close()
+
+
+def test_paper_case_f32_follows_the_transient():
+    w = I.PAPER_COLLECTOR_360x180
+    t, flags = w.types(), w.extra["flags"]
+    o = oracle.Lattice(t, w.tau, w.u_peak, flags=flags)
+    g = lbm.Lattice(t, w.tau, w.u_peak, precision=lbm.LBM_F32, flags=flags)
+    o.run(1000, 0.0, 100)
+    g.run(1000, 0.0, 100)
+    du, dr = _rel_fields(t, g.macro(), o.macro())
+    assert du < 1e-5 and dr < 1e-5, (du, dr)
+    g.close()
