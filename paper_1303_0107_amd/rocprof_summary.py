@@ -13,6 +13,8 @@ the mean of every counter it holds per dispatch.
 import argparse
 import collections
 import csv
+import re
+import subprocess
 
 
 SHORT = [("lbm::OffsetCell<float, float, float>", "F32Cell"),
@@ -23,8 +25,33 @@ SHORT = [("lbm::OffsetCell<float, float, float>", "F32Cell"),
          ("lbm::sweep::", ""), ("lbm::", "")]
 
 
+# Mangled blocked-sweep names that c++filt leaves alone (it does not know the
+# _Float16 mangling): tb_kernel / tb_batch_kernel of an offset cell.
+_TB = re.compile(r"_ZN3lbm5sweep(\d+)(tb_kernel|tb_batch_kernel)INS_10OffsetCellI"
+                 r"(DF16_|14__hip_bfloat16|f)ffEE((?:L[ib]\d+E)+)")
+_CELL = {"DF16_": "H16Cell", "14__hip_bfloat16": "BF16Cell", "f": "F32Cell"}
+
+
+def demangle(name: str) -> str:
+    """The readable form of a mangled kernel name (c++filt), else the name."""
+    if not name.startswith("_Z"):
+        return name
+    m = _TB.match(name)
+    if m:
+        args = []
+        for kind, v in re.findall(r"L([ib])(\d+)E", m.group(4)):
+            args.append(v if kind == "i" else ("true" if v == "1" else "false"))
+        return f"{m.group(2)}<{_CELL[m.group(3)]}, {', '.join(args)}>"
+    try:
+        out = subprocess.run(["c++filt", name], capture_output=True, text=True, timeout=10)
+        return out.stdout.strip() or name
+    except (OSError, subprocess.SubprocessError):
+        return name
+
+
 def short(name: str) -> str:
     """Kernel name with the cell policy abbreviated and the argument list cut."""
+    name = demangle(name)
     for a, b in SHORT:
         name = name.replace(a, b)
     return name.split("(")[0]

@@ -41,3 +41,9 @@ def test_kernel_names_keep_anonymous_namespace_kernels():
                    "namespace)::Cand const*)") == "narrow_kernel<16>"
     assert R.short("void lbm::sweep::tb_kernel<lbm::OffsetCell<float, float, float>, 32, 9>"
                    "(args)") == "tb_kernel<F32Cell, 32, 9>"
+
+
+def test_mangled_half_precision_sweep_names():
+    name = ("_ZN3lbm5sweep9tb_kernelINS_10OffsetCellIDF16_ffEELi32ELi9ELi1024ELi0ELb0ELb1EEEv"
+            "NS_9SweepArgsINT_1TEEEPKii")
+    assert R.short(name) == "tb_kernel<H16Cell, 32, 9, 1024, 0, false, true>"
