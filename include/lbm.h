@@ -285,7 +285,10 @@ int lbm_set_state(lbm_handle *h, const double *f, size_t n);
  * those the first exchange step and outlet statistics make, with the
  * candidate lists at their initial capacity (max(4096, nx*ny/16) per kind).
  * A lattice with more interface cells of one kind than that grows its lists
- * on an exchange step and then holds more than this count. */
+ * on an exchange step and then holds more than this count.  Not counted: the
+ * staging field of 24 bytes per cell that lbm_get_macro, lbm_get_state,
+ * lbm_set_state and an exchange step given a host field make on first use
+ * (the optimisation loop and the server need none of them). */
 size_t lbm_footprint_bytes(const lbm_geometry_desc *d);
 
 /* Release a handle (NULL is ignored).  The call waits for the handle's

@@ -475,7 +475,6 @@ size_t footprint(int nx, int ny, int precision) {
     const size_t ntiles = max_tile_count(nx, ny, precision);
     b += c(std::max((size_t)sweep_blocks(nx, ny), ntiles) * 4 * sizeof(double));
     b += c(ntiles * sizeof(int32_t));
-    b += c(3 * N * sizeof(double));          // macro field (exchange step)
     // exchange step, allocated on the first one: the two candidate lists at
     // their initial capacity, the selection scratch and the selections (each
     // at most that capacity); the lists grow when a lattice has more
@@ -1621,13 +1620,14 @@ void exchange_keys(Exchange &e) {
     lbm_handle *h = e.h;
     const size_t N = h->N();
     HIP_TRY(hipSetDevice(h->device));
-    h->macro.ensure(3 * N * sizeof(double));
-    double *m = h->macro.as<double>();
+    // The keys read the field the caller gave, else the stored state itself
+    // (only the interface cells and their neighbours).
+    const double *m = nullptr;
     if (e.field) {
-        HIP_TRY(hipMemcpyAsync(m, e.field, 3 * N * sizeof(double), hipMemcpyHostToDevice,
-                               h->stream));
-    } else {
-        macro_dispatch(h);
+        h->macro.ensure(3 * N * sizeof(double));
+        HIP_TRY(hipMemcpyAsync(h->macro.p, e.field, 3 * N * sizeof(double),
+                               hipMemcpyHostToDevice, h->stream));
+        m = h->macro.as<double>();
     }
     ensure_pinned(h, 64 * sizeof(double));
     // candidate lists: 2 x (u64 key, u64 hash, i32 idx) per entry
@@ -1641,8 +1641,11 @@ void exchange_keys(Exchange &e) {
     KeysArgs ka;
     ka.types = h->types.as<uint8_t>();
     ka.rho = m;
-    ka.ux = m + N;
-    ka.uy = m + 2 * N;
+    ka.ux = m ? m + N : nullptr;
+    ka.uy = m ? m + 2 * N : nullptr;
+    ka.f = h->f[h->cur].p;
+    ka.plane = h->plane;
+    ka.pitch = h->pitch;
     ka.nx = h->nx;
     ka.ny = h->ny;
     ka.band_x = e.p.band_x;
@@ -1659,7 +1662,7 @@ void exchange_keys(Exchange &e) {
     ka.hs = kf + 3 * cap;
     ka.if_ = reinterpret_cast<int32_t *>(kf + 4 * cap);
     ka.is = ka.if_ + cap;
-    HIP_TRY(launch_keys(ka, h->stream));
+    with_storage(h->precision, [&](auto t) { HIP_TRY(launch_keys<decltype(t)>(ka, h->stream)); });
     HIP_TRY(hipMemcpyAsync(h->pinned, counters, 5 * sizeof(unsigned long long),
                            hipMemcpyDeviceToHost, h->stream));
 }
@@ -1709,8 +1712,18 @@ void exchange_select(Exchange &e) {
     int *err = exchange_error(h);
     HIP_TRY(launch_select_pair(kf, hf, if_, (int64_t)e.cnt[0], ks, hs, is, (int64_t)e.cnt[1], keff,
                                srem, sadd, h->select_tmp.p, keff, err, h->stream));
-    HIP_TRY(launch_flip(h->types.as<uint8_t>(), srem, sadd, (int)keff, rrho,
-                        h->macro.as<double>(), h->stream));
+    FlipArgs fa;
+    fa.types = h->types.as<uint8_t>();
+    fa.removed = srem;
+    fa.added = sadd;
+    fa.k_eff = (int)keff;
+    fa.removed_rho = rrho;
+    fa.rho = e.field ? h->macro.as<double>() : nullptr;
+    fa.f = h->f[h->cur].p;
+    fa.plane = h->plane;
+    fa.nx = h->nx;
+    fa.pitch = h->pitch;
+    with_storage(h->precision, [&](auto t) { HIP_TRY(launch_flip<decltype(t)>(fa, h->stream)); });
     if (e.p.reinit == LBM_WARM)  // removed and added cells, adjacent in sel
         with_storage(h->precision,
                      [&](auto t) { zero_cells<decltype(t)>(h, srem, 2 * (int)keff); });

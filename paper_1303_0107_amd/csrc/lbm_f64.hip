@@ -12,6 +12,7 @@
 #include <stdint.h>
 
 #include "lbm_internal.h"
+#include "lbm_keys.h"
 
 #pragma clang fp contract(off)
 
@@ -41,6 +42,21 @@ __device__ __forceinline__ void moments(const double (&f)[9], double &r,
         my += kCy[i] * f[i];
     }
 }
+
+// Density and velocity of cell n (pitched) of the stored state: the
+// macroscopic export and the exchange-step keys both use this.
+struct Moments {
+    using T = double;
+    __device__ static __forceinline__ void at(const double *f, size_t plane, size_t n,
+                                              double &r, double &ux, double &uy) {
+        double g[9], mx, my;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) g[i] = f[(size_t)i * plane + n];
+        moments(g, r, mx, my);
+        ux = mx / r;
+        uy = my / r;
+    }
+};
 
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], int tid) {
@@ -123,14 +139,7 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroArgs<double> a) {
     const size_t n = (size_t)y * a.pitch + x;
     const size_t l = (size_t)y * a.nx + x;
     double r = 0.0, ux = 0.0, uy = 0.0;
-    if (cell_type(a.cell[n]) != kSolid) {
-        double f[9], mx, my;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = a.f[(size_t)i * a.plane + n];
-        moments(f, r, mx, my);
-        ux = mx / r;
-        uy = my / r;
-    }
+    if (cell_type(a.cell[n]) != kSolid) Moments::at(a.f, a.plane, n, r, ux, uy);
     if (a.rho) {
         a.rho[l] = r;
         a.ux[l] = ux;
@@ -304,6 +313,16 @@ template <>
 hipError_t launch_macro<double>(const MacroArgs<double> &a, hipStream_t s) {
     hipLaunchKernelGGL(f64::macro_kernel, grid_cells(a.nx, a.ny), dim3(64, 4), 0, s, a);
     return hipGetLastError();
+}
+
+template <>
+hipError_t launch_keys<double>(const KeysArgs &a, hipStream_t s) {
+    return keys::launch_keys<f64::Moments>(a, s);
+}
+
+template <>
+hipError_t launch_flip<double>(const FlipArgs &a, hipStream_t s) {
+    return keys::launch_flip<f64::Moments>(a, s);
 }
 
 template <>

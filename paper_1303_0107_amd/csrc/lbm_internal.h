@@ -132,9 +132,14 @@ struct MacroArgs {
     size_t plane;
 };
 
+// Exchange-step keys: from the field (rho, ux, uy; logical layout) when rho
+// is given, else from the stored state f (storage of the handle, pitched).
 struct KeysArgs {
     const uint8_t *types;  // logical layout
     const double *rho, *ux, *uy;
+    const void *f;
+    size_t plane;
+    int pitch;
     int nx, ny, band_x, band_y, criterion;
     uint64_t seed;
     int64_t cap;
@@ -266,6 +271,7 @@ template <typename T>
 hipError_t launch_digest(const T *f, const uint16_t *cell, const uint8_t *types, int nx,
                          int ny, int pitch, size_t plane, unsigned long long *out,
                          hipStream_t s);
+template <typename T>
 hipError_t launch_keys(const KeysArgs &a, hipStream_t s);
 // The k_eff first of the nf fluid and of the ns solid candidates, each list in
 // the order (key, hash), written as cell indices to sel_f and sel_s.
@@ -278,10 +284,21 @@ hipError_t launch_select_pair(const uint64_t *kf, const uint64_t *hf, const int3
                               const int32_t *is, int64_t ns, int64_t k_eff, int32_t *sel_f,
                               int32_t *sel_s, void *scratch, int64_t k_max, int *error,
                               hipStream_t s);
-// Flip the selected cells; removed_rho[k] = rho[removed[k]].
-hipError_t launch_flip(uint8_t *types, const int32_t *removed,
-                       const int32_t *added, int k_eff, double *removed_rho,
-                       const double *rho, hipStream_t s);
+// Flip the selected cells; removed_rho[k] = the density of cell removed[k],
+// from the field rho (logical layout) when given, else from the stored state
+// f (storage T, pitched).
+struct FlipArgs {
+    uint8_t *types;
+    const int32_t *removed, *added;
+    int k_eff;
+    double *removed_rho;
+    const double *rho;
+    const void *f;
+    size_t plane;
+    int nx, pitch;
+};
+template <typename T>
+hipError_t launch_flip(const FlipArgs &a, hipStream_t s);
 
 // Double-precision specialisations, defined in lbm_f64.hip.
 template <>
@@ -299,6 +316,10 @@ hipError_t launch_step_batch<double>(const SweepArgs<double> *args, const int32_
                                      hipStream_t s);
 template <>
 hipError_t launch_macro<double>(const MacroArgs<double> &a, hipStream_t s);
+template <>
+hipError_t launch_keys<double>(const KeysArgs &a, hipStream_t s);
+template <>
+hipError_t launch_flip<double>(const FlipArgs &a, hipStream_t s);
 template <>
 hipError_t launch_mass<double>(const MacroArgs<double> &a, double *partials, hipStream_t s);
 template <>

@@ -25,6 +25,7 @@
 #include <cstring>
 
 #include "lbm_internal.h"
+#include "lbm_keys.h"
 #include "lbm_sweep.h"
 
 namespace lbm {
@@ -47,6 +48,24 @@ __device__ __forceinline__ void moments_sym(const double (&d)[9], double &dr,
     jx = (d[1] + (d[5] + d[8])) - (d[3] + (d[6] + d[7]));
     jy = (d[2] + (d[5] + d[6])) - (d[4] + (d[8] + d[7]));
 }
+
+// Density and velocity (Eq. 2) of the stored offsets of cell n (pitched), in
+// double: the macroscopic export and the exchange-step keys both use this.
+template <typename S>
+struct OffsetMoments {
+    using T = S;
+    __device__ static __forceinline__ void at(const S *f, size_t plane, size_t n, double &rho,
+                                              double &ux, double &uy) {
+        double d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) d[i] = Sto<S>::to_d(f[(size_t)i * plane + n]);
+        double dr, jx, jy;
+        moments_sym(d, dr, jx, jy);
+        rho = 1.0 + dr;
+        ux = jx / rho;
+        uy = jy / rho;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Wavefront / block reductions of NV doubles (fixed order: results do not
@@ -276,16 +295,7 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroArgs<T> a) {
     const size_t l = (size_t)y * a.nx + x;
     const bool solid = cell_type(a.cell[n]) == kSolid;
     double rho = 0.0, ux = 0.0, uy = 0.0;
-    if (!solid) {
-        double d[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) d[i] = Sto<T>::to_d(a.f[(size_t)i * a.plane + n]);
-        double dr, jx, jy;
-        moments_sym(d, dr, jx, jy);
-        rho = 1.0 + dr;
-        ux = jx / rho;
-        uy = jy / rho;
-    }
+    if (!solid) OffsetMoments<T>::at(a.f, a.plane, n, rho, ux, uy);
     if (a.rho) {
         a.rho[l] = rho;
         a.ux[l] = ux;
@@ -502,129 +512,9 @@ __global__ __launch_bounds__(256) void import_plane_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Exchange step (Sec. 2.2).
-__device__ __forceinline__ uint64_t splitmix64(uint64_t state) {
-    // SplitMix64 output function (Steele, Lea & Flood 2014) on state + gamma
-    uint64_t z = state + 0x9e3779b97f4a7c15ull;
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
-// Order-preserving integer image of a key >= 0 (-0 folded onto +0).
-__device__ __forceinline__ uint64_t key_bits(double k) {
-    return k == 0.0 ? 0ull : (uint64_t)__double_as_longlong(k);
-}
-
-// Candidate keys of the interface cells inside the band.  Fluid candidates
-// sort ascending on (key, hash, idx); solid candidates descending on key,
-// which is stored complemented so that both lists sort ascending.
-// Blocks of 64 x 16 cells (16 waves, one row each): the candidates' list
-// slots are claimed with one atomic per block and list.
-constexpr int kKeysRows = 16;
-__global__ __launch_bounds__(64 * kKeysRows) void keys_kernel(KeysArgs a) {
-#pragma clang fp contract(off)
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * kKeysRows + threadIdx.y;
-    const int nx = a.nx;
-    const bool in_band = x >= a.band_x && x <= a.nx - 1 - a.band_x && y >= a.band_y &&
-                         y <= a.ny - 1 - a.band_y;
-    const size_t l = in_band ? (size_t)y * nx + x : 0;
-    const uint8_t t = in_band ? a.types[l] : (uint8_t)0xff;
-    const int ddx[4] = {1, 0, -1, 0};
-    const int ddy[4] = {0, 1, 0, -1};
-    bool touch = false;
-    double key = 0.0;
-    bool bad = false;
-    if (t == kFluid) {
-#pragma unroll
-        for (int d = 0; d < 4; ++d)
-            touch |= a.types[l + ddx[d] + (ptrdiff_t)ddy[d] * nx] == kSolid;
-        if (touch) {
-            const double ux = a.ux[l], uy = a.uy[l];
-            const double t1 = ux * ux;
-            const double t2 = uy * uy;
-            const double t3 = t1 + t2;
-            key = a.criterion == kCritPaper ? a.rho[l] * t3 : t3;
-        }
-    } else if (t == kSolid) {
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const size_t m = l + ddx[d] + (ptrdiff_t)ddy[d] * nx;
-            if (a.types[m] == kSolid) continue;
-            touch = true;
-            if (a.criterion == kCritPaper) {
-                const double tang = ddx[d] != 0 ? fabs(a.uy[m]) : fabs(a.ux[m]);
-                key = key + tang;
-            } else {
-                const double t1 = a.ux[m] * a.ux[m];
-                const double t2 = a.uy[m] * a.uy[m];
-                const double s = t1 + t2;
-                if (!(s >= 0.0)) bad = true;
-                if (s > key) key = s;
-            }
-        }
-    }
-    if (touch && !(key >= 0.0)) bad = true;
-    if (bad) atomicOr(a.error, 1);
-    const bool is_f = touch && !bad && t == kFluid, is_s = touch && !bad && t == kSolid;
-    // One counter update per block and list: each wave (a row of the block)
-    // counts its candidates, thread 0 claims the block's slots, and lane k of
-    // wave w takes slot base + (candidates of waves < w) + (candidates of the
-    // wave below lane k).
-    __shared__ unsigned wave_n[2][kKeysRows];
-    __shared__ unsigned long long block_base[2];
-    const int lane = threadIdx.x, w = threadIdx.y;
-    const uint64_t below = (1ull << lane) - 1ull;
-    const uint64_t mf = __ballot(is_f), ms = __ballot(is_s);
-    if (lane == 0) {
-        wave_n[0][w] = (unsigned)__popcll(mf);
-        wave_n[1][w] = (unsigned)__popcll(ms);
-    }
-    __syncthreads();
-    if (w == 0 && lane < 2) {
-        unsigned long long tot = 0;
-        for (int k = 0; k < kKeysRows; ++k) tot += wave_n[lane][k];
-        block_base[lane] = tot ? atomicAdd(lane == 0 ? a.count_f : a.count_s, tot) : 0ull;
-    }
-    __syncthreads();
-    unsigned long long bf = block_base[0], bs = block_base[1];
-    for (int k = 0; k < w; ++k) {
-        bf += wave_n[0][k];
-        bs += wave_n[1][k];
-    }
-    if (!is_f && !is_s) return;
-    const uint64_t kb = key_bits(key);
-    const uint64_t h = splitmix64(a.seed + (uint64_t)l);
-    if (is_f) {
-        const unsigned long long s = bf + (unsigned long long)__popcll(mf & below);
-        if (s < (unsigned long long)a.cap) {
-            a.kf[s] = kb;
-            a.hf[s] = h;
-            a.if_[s] = (int32_t)l;
-        }
-    } else {
-        const unsigned long long s = bs + (unsigned long long)__popcll(ms & below);
-        if (s < (unsigned long long)a.cap) {
-            a.ks[s] = ~kb;
-            a.hs[s] = h;
-            a.is[s] = (int32_t)l;
-        }
-    }
-}
-
-// Apply the exchange to the logical type map.
-// Flip the selected cells and record the density of each removed one, in
-// selection order.
-__global__ void flip_kernel(uint8_t *types, const int32_t *removed,
-                            const int32_t *added, int k_eff, const double *rho,
-                            double *removed_rho) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= k_eff) return;
-    removed_rho[k] = rho[removed[k]];
-    types[removed[k]] = kSolid;
-    types[added[k]] = kFluid;
-}
+// Exchange step (Sec. 2.2): the keys and flip kernels live in lbm_keys.h; the
+// state digest below uses the same SplitMix64.
+using keys::splitmix64;
 
 // ---------------------------------------------------------------------------
 // Host-side launchers.
@@ -778,20 +668,14 @@ hipError_t launch_import_plane(T *f, const uint16_t *cell, const double *in,
     return hipGetLastError();
 }
 
+template <typename T>
 hipError_t launch_keys(const KeysArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(keys_kernel,
-                       dim3((unsigned)((a.nx + 63) / 64), (unsigned)((a.ny + kKeysRows - 1) / kKeysRows)),
-                       dim3(64, kKeysRows), 0, s, a);
-    return hipGetLastError();
+    return keys::launch_keys<OffsetMoments<T>>(a, s);
 }
 
-hipError_t launch_flip(uint8_t *types, const int32_t *removed,
-                       const int32_t *added, int k_eff, double *removed_rho,
-                       const double *rho, hipStream_t s) {
-    if (k_eff <= 0) return hipSuccess;
-    hipLaunchKernelGGL(flip_kernel, dim3((k_eff + 255) / 256), dim3(256), 0, s,
-                       types, removed, added, k_eff, rho, removed_rho);
-    return hipGetLastError();
+template <typename T>
+hipError_t launch_flip(const FlipArgs &a, hipStream_t s) {
+    return keys::launch_flip<OffsetMoments<T>>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -865,7 +749,9 @@ template hipError_t launch_digest<bf16>(const bf16 *, const uint16_t *, const ui
     template hipError_t launch_export_plane<T>(const T *, const uint16_t *, double *, int,   \
                                                int, int, int, size_t, hipStream_t);          \
     template hipError_t launch_import_plane<T>(T *, const uint16_t *, const double *, int,   \
-                                               int, int, int, size_t, hipStream_t);
+                                               int, int, int, size_t, hipStream_t);          \
+    template hipError_t launch_keys<T>(const KeysArgs &, hipStream_t);                       \
+    template hipError_t launch_flip<T>(const FlipArgs &, hipStream_t);
 LBM_OFFSET_INST(float)
 LBM_OFFSET_INST(h16)
 LBM_OFFSET_INST(bf16)

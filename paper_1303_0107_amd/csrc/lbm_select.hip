@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "lbm_internal.h"
 
@@ -35,6 +36,11 @@ constexpr int kNarrowThreads = 1024;
 constexpr int kNarrowCached = 16;  // candidates per thread kept in registers
 constexpr int kRankRows = 256, kRankCols = 128;
 constexpr int kPassThreads = 256, kMaxPassBlocks = 512;
+// Multi-block passes queued for a long list (each launch costs a few
+// microseconds even when the select is already done); what they leave is
+// finished by one workgroup per list.  On the distributors' lists (45k-150k
+// candidates) 2 to 16 queued passes measured the same within noise.
+constexpr int kPassLaunches = 4;
 
 struct Cand {
     const uint64_t *key, *hash;
@@ -203,15 +209,17 @@ __device__ __forceinline__ bool narrow_decide(Narrow &s, int lane, const Cand &c
     return true;
 }
 
-// Block b finds the composite of rank r of list b.  With CACHED > 0 every
+// Block b finds the composite of rank r of list b (RESUME: continues the
+// select from the state the multi-block passes left, when they did not finish).  With CACHED > 0 every
 // thread keeps its (at most CACHED) candidates in registers for all the
 // passes (lists of at most CACHED * kNarrowThreads entries); otherwise each
 // pass reads the list again.
-template <int CACHED>
+template <int CACHED, bool RESUME>
 __global__ __launch_bounds__(kNarrowThreads) void narrow_kernel(Cand c0, Cand c1, int64_t r,
                                                                 SelState *st) {
     const Cand c = blockIdx.x == 0 ? c0 : c1;
     const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    if (RESUME && st->nar[b].done) return;  // the passes found it: same for every thread
     __shared__ unsigned hist[256];
     __shared__ int64_t witness[256];
     __shared__ unsigned long long kmin[256], kmax[256];
@@ -219,10 +227,14 @@ __global__ __launch_bounds__(kNarrowThreads) void narrow_kernel(Cand c0, Cand c1
     __shared__ int64_t s_thr;
     __shared__ int s_err;
     if (tid == 0) {
-        ns.pk = ns.ph = ns.mk = ns.mh = 0ull;
-        ns.rr = r;
-        ns.d = 0;
-        ns.done = 0;
+        if (RESUME) {
+            ns = st->nar[b];  // where the multi-block passes stopped
+        } else {
+            ns.pk = ns.ph = ns.mk = ns.mh = 0ull;
+            ns.rr = r;
+            ns.d = 0;
+            ns.done = 0;
+        }
         s_thr = -1;
         s_err = 0;
     }
@@ -539,6 +551,16 @@ Layout layout(int64_t k_max) {
 
 size_t select_scratch_bytes(int64_t k_max) { return layout(k_max).total; }
 
+// Multi-block pass launches before the one-workgroup finish
+// (LBM_NARROW_PASSES overrides it, 0..16).
+static int pass_launches() {
+    static const int v = [] {
+        const char *e = std::getenv("LBM_NARROW_PASSES");
+        return e ? std::min(16, std::max(0, std::atoi(e))) : kPassLaunches;
+    }();
+    return v;
+}
+
 hipError_t launch_select_pair(const uint64_t *kf, const uint64_t *hf, const int32_t *if_,
                               int64_t nf, const uint64_t *ks, const uint64_t *hs,
                               const int32_t *is, int64_t ns, int64_t k_eff, int32_t *sel_f,
@@ -560,16 +582,19 @@ hipError_t launch_select_pair(const uint64_t *kf, const uint64_t *hf, const int3
     for (int64_t lo = 0; lo < k_eff; lo += L.cap) {
         const int64_t hi = std::min(k_eff, lo + L.cap), m = hi - lo;
         if (nmax <= kNarrowCached * kNarrowThreads) {
-            hipLaunchKernelGGL(narrow_kernel<kNarrowCached>, dim3(2), dim3(kNarrowThreads), 0, s,
-                               c0, c1, hi - 1, st);
+            hipLaunchKernelGGL((narrow_kernel<kNarrowCached, false>), dim3(2),
+                               dim3(kNarrowThreads), 0, s, c0, c1, hi - 1, st);
         } else {
-            // long lists: one multi-block launch per byte (at most 16)
+            // long lists: a few multi-block launches, one per byte, then one
+            // workgroup per list finishes the select if they did not
             const unsigned blocks = (unsigned)std::min<int64_t>(
                 kMaxPassBlocks, (nmax + 4 * kPassThreads - 1) / (4 * kPassThreads));
             hipLaunchKernelGGL(narrow_init_kernel, dim3(2), dim3(256), 0, s, st, hi - 1);
-            for (int pass = 0; pass < 16; ++pass)
+            for (int pass = 0; pass < pass_launches(); ++pass)
                 hipLaunchKernelGGL(narrow_pass_kernel, dim3(blocks, 2), dim3(kPassThreads), 0, s,
                                    c0, c1, st);
+            hipLaunchKernelGGL((narrow_kernel<0, true>), dim3(2), dim3(kNarrowThreads), 0, s, c0,
+                               c1, hi - 1, st);
         }
         hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)std::min<int64_t>(1024, (2 * m + 255) / 256)),
                            dim3(256), 0, s, rank, 2 * L.cap);
