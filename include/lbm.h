@@ -291,6 +291,12 @@ int lbm_set_state(lbm_handle *h, const double *f, size_t n);
  * (the optimisation loop and the server need none of them). */
 size_t lbm_footprint_bytes(const lbm_geometry_desc *d);
 
+/* Device bytes handle h holds now (each buffer in its size class), for
+ * checking lbm_footprint_bytes: after the first exchange step and outlet
+ * statistics it equals the footprint unless a candidate list grew or one of
+ * the calls that stage a whole field ran.  Errors: LBM_EINVAL (NULL). */
+int lbm_device_bytes(lbm_handle *h, size_t *bytes);
+
 /* Release a handle (NULL is ignored).  The call waits for the handle's
  * stream; its device blocks and pinned staging then go to a process-wide
  * cache that later handles and batches of the same size classes draw from
@@ -522,7 +528,8 @@ typedef struct {
     int64_t cell_steps;      /* sum over sessions of nx * ny * steps taken      */
     int64_t nonsolid_cell_steps;
     double busy_seconds;     /* time in rounds (device work and host events)    */
-    double admit_seconds;    /* of which: creating admitted sessions            */
+    double admit_seconds;    /* creating admitted sessions, on the creation     */
+                             /* thread (overlaps the rounds; not in busy)       */
     double sweep_seconds;    /*           batched sweeps (incl. batch rebuilds) */
     double event_seconds;    /*           exchange steps and completions        */
     size_t peak_bytes;       /* largest admitted footprint sum                  */

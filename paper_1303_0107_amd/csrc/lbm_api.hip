@@ -393,6 +393,15 @@ struct lbm_handle {
         for (Graph &g : graphs) (void)hipGraphExecDestroy(g.exec);
         graphs.clear();
     }
+    // Device bytes the handle holds (each block in its size class).
+    size_t device_bytes() {
+        DeviceBuffer *bufs[] = {&f[0], &f[1], &cell, &types, &uin, &uprev, &partials,
+                                &red, &out_rows, &bnd, &macro, &cand, &sel, &select_tmp,
+                                &tiles, &ctl};
+        size_t b = 0;
+        for (DeviceBuffer *x : bufs) b += x->bytes;
+        return b;
+    }
     // Hand every device block and both pinned staging areas to the caches;
     // the caller has synchronised the stream.
     void recycle() {
@@ -485,6 +494,10 @@ size_t footprint(int nx, int ny, int precision) {
     b += c((size_t)cap * (sizeof(double) + 2 * sizeof(int32_t)));
     // the outlet sums of lbm_outlet_stats
     b += c((size_t)(2 * (2 * ny + 5) + 1) * sizeof(double));
+    // reduction results, run control, outlet rows (at most one run per two rows)
+    b += c(64 * sizeof(double));
+    b += c(sizeof(RunControl));
+    b += c(2 * (size_t)std::max(1, (ny + 1) / 2) * sizeof(int32_t));
     return b;
 }
 
@@ -1229,6 +1242,24 @@ size_t lbm_footprint_bytes(const lbm_geometry_desc *d) {
     std::string why;
     if (!check_desc(d, why)) return 0;
     return footprint(d->nx, d->ny, d->precision);
+}
+
+}  // extern "C"
+
+namespace lbm {
+void handle_set_stream(lbm_handle *h, hipStream_t s) {
+    h->drop_graphs();  // captured for the old stream
+    h->stream = s;
+}
+}  // namespace lbm
+
+extern "C" {
+
+int lbm_device_bytes(lbm_handle *h, size_t *bytes) {
+    g_error.clear();
+    if (!h || !bytes) return fail(LBM_EINVAL, "null argument");
+    *bytes = h->device_bytes();
+    return LBM_OK;
 }
 
 int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,

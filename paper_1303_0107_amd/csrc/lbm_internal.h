@@ -8,6 +8,8 @@
 
 #include <type_traits>
 
+struct lbm_handle;
+
 namespace lbm {
 
 enum : uint32_t { kSolid = 0, kFluid = 1, kInlet = 2, kOutlet = 3 };
@@ -299,6 +301,11 @@ struct FlipArgs {
 };
 template <typename T>
 hipError_t launch_flip(const FlipArgs &a, hipStream_t s);
+
+// Move a handle's device work to another stream (the request server makes
+// handles on a stream of its own, then runs them on the worker's).  The
+// caller has synchronised the handle's current stream.
+void handle_set_stream(lbm_handle *h, hipStream_t s);
 
 // Double-precision specialisations, defined in lbm_f64.hip.
 template <>

@@ -1,13 +1,16 @@
 // Request loop with continuous batching, built on the library's C ABI.
 //
-// One worker thread owns all device work.  Each round it admits queued
-// requests in arrival order while the summed footprint of the active
-// sessions stays within the budget, advances every active session by the
-// same number of time steps (one batch per storage precision), and then lets
-// sessions that reached an event take it: an optimisation iteration's
-// exchange step (Sec. 2.2), or completion (outlet statistics of Sec. 4.2,
-// state digest, release of the device memory).  Submitting threads only
-// touch the queues, under one mutex.
+// One worker thread owns the device work of the running sessions.  Each
+// round it admits queued requests in arrival order while the summed
+// footprint of the admitted sessions stays within the budget, advances every
+// running session by the same number of time steps (one batch per storage
+// precision), and then lets sessions that reached an event take it: an
+// optimisation iteration's exchange step (Sec. 2.2), or completion (outlet
+// statistics of Sec. 4.2, state digest, release of the device memory).
+// Admitted sessions are created by a second thread on a stream of its own
+// (the host-side map generation and uploads overlap the rounds) and join the
+// rounds once created, their handles moved to the worker's stream.
+// Submitting threads only touch the queues; every queue is under one mutex.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +25,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "lbm_internal.h"
 
 namespace {
 
@@ -71,6 +75,9 @@ struct lbm_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Session> queue;          // submitted, not admitted
+    std::deque<Session> to_create;      // admitted, handle not made yet
+    std::deque<Session> created;        // handle made (or failed), not yet running
+    std::condition_variable cv_create;
     std::deque<lbm_result> results;     // completed, not polled
     uint64_t next_id = 1;
     int64_t pending = 0;                // submitted and not completed
@@ -81,8 +88,12 @@ struct lbm_server {
     std::vector<Session> active;
     std::map<int, Group> groups;
     std::map<int, std::pair<int32_t, int32_t>> tuned;  // precision -> (variant, order)
-    size_t used = 0;
+    size_t used = 0;        // footprint of the admitted sessions
+    int64_t creating = 0;   // admitted sessions not yet running
     std::thread worker;
+    // creation thread
+    std::thread creator;
+    hipStream_t create_stream = nullptr;
 
     void complete(Session &s) {
         lbm_result r{};
@@ -164,15 +175,12 @@ struct lbm_server {
         groups.erase(it);
     }
 
-    void admit(std::vector<Session> &incoming) {
-        const double t0 = now_seconds();
-        for (Session &s : incoming) {
-            s.t_admit = now_seconds();
-            used += s.bytes;
-            const int rc = lbm_create_geometry(&s.req.geom, nullptr, stream, &s.h);
-            if (rc != LBM_OK) {
-                s.status = rc;
-                s.h = nullptr;
+    // Sessions whose handles the creation thread has made: failed ones
+    // complete, the others take the events due at step 0 and start running.
+    void start(std::vector<Session> &made) {
+        for (Session &s : made) {
+            --creating;
+            if (s.status != LBM_OK) {  // no handle: release the budget it held
                 used -= s.bytes;
                 complete(s);
                 continue;
@@ -186,11 +194,37 @@ struct lbm_server {
             }
             active.push_back(s);
         }
-        std::lock_guard<std::mutex> g(mu);
-        st.peak_bytes = std::max(st.peak_bytes, used);
-        const double dt = now_seconds() - t0;
-        st.admit_seconds += dt;
-        st.busy_seconds += dt;
+    }
+
+    // The creation thread: makes each admitted session's handle on its own
+    // stream, then moves the handle to the worker's stream.
+    void create_loop() {
+        (void)hipSetDevice(device);
+        for (;;) {
+            Session s;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_create.wait(lk, [&] { return stop || !to_create.empty(); });
+                if (stop) return;
+                s = to_create.front();
+                to_create.pop_front();
+            }
+            const double t0 = now_seconds();
+            s.t_admit = t0;
+            const int rc = lbm_create_geometry(&s.req.geom, nullptr, create_stream, &s.h);
+            if (rc == LBM_OK) {
+                lbm::handle_set_stream(s.h, stream);
+            } else {
+                s.status = rc;
+                s.h = nullptr;
+            }
+            {
+                std::lock_guard<std::mutex> g(mu);
+                created.push_back(s);
+                st.admit_seconds += now_seconds() - t0;
+            }
+            cv_work.notify_one();
+        }
     }
 
     // Batch configuration: the configured one, else the autotuner's choice,
@@ -282,24 +316,42 @@ struct lbm_server {
     void run() {
         (void)hipSetDevice(device);
         for (;;) {
-            std::vector<Session> incoming;
+            std::vector<Session> made;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+                auto admissible = [&] {
+                    return !queue.empty() &&
+                           (int64_t)active.size() + creating < (int64_t)cfg.max_sessions &&
+                           used + queue.front().bytes <= cfg.hbm_budget;
+                };
+                cv_work.wait(lk, [&] {
+                    return stop || admissible() || !created.empty() || !active.empty();
+                });
                 if (stop) break;
-                size_t budget_used = used;
-                size_t n_active = active.size();
-                while (!queue.empty() && n_active < (size_t)cfg.max_sessions &&
-                       budget_used + queue.front().bytes <= cfg.hbm_budget) {
-                    budget_used += queue.front().bytes;
-                    ++n_active;
-                    incoming.push_back(queue.front());
+                // admit in arrival order: the budget is taken now, the handle is
+                // made by the creation thread
+                bool any = false;
+                while (admissible()) {
+                    Session &q = queue.front();
+                    used += q.bytes;
+                    ++creating;
+                    to_create.push_back(q);
                     queue.pop_front();
                     ++st.active;
                     --st.queued;
+                    any = true;
                 }
+                st.peak_bytes = std::max(st.peak_bytes, used);
+                if (any) cv_create.notify_one();
+                made.assign(created.begin(), created.end());
+                created.clear();
             }
-            if (!incoming.empty()) admit(incoming);
+            if (!made.empty()) {
+                const double t0 = now_seconds();
+                start(made);
+                std::lock_guard<std::mutex> g(mu);
+                st.busy_seconds += now_seconds() - t0;
+            }
             if (!active.empty()) round();
         }
         for (auto &kv : groups)
@@ -327,9 +379,27 @@ int lbm_server_create(const lbm_server_config *cfg, void *hip_stream, lbm_server
         delete s;
         return LBM_EHIP;
     }
+    if (hipStreamCreateWithFlags(&s->create_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return LBM_EHIP;
+    }
     try {
         s->worker = std::thread([s] { s->run(); });
     } catch (...) {
+        (void)hipStreamDestroy(s->create_stream);
+        delete s;
+        return LBM_ENOMEM;
+    }
+    try {
+        s->creator = std::thread([s] { s->create_loop(); });
+    } catch (...) {
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stop = true;
+        }
+        s->cv_work.notify_all();
+        s->worker.join();
+        (void)hipStreamDestroy(s->create_stream);
         delete s;
         return LBM_ENOMEM;
     }
@@ -404,7 +474,13 @@ void lbm_server_destroy(lbm_server *s) {
         s->stop = true;
     }
     s->cv_work.notify_all();
+    s->cv_create.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    if (s->creator.joinable()) s->creator.join();
+    // handles made but never run
+    for (Session &x : s->created)
+        if (x.h) lbm_destroy(x.h);
+    (void)hipStreamDestroy(s->create_stream);
     delete s;
 }
 

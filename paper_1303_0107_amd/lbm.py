@@ -128,6 +128,7 @@ def load() -> ctypes.CDLL:
         "lbm_get_state": (ctypes.c_int, [H, P, sz]),
         "lbm_set_state": (ctypes.c_int, [H, P, sz]),
         "lbm_footprint_bytes": (sz, [P]),
+        "lbm_device_bytes": (ctypes.c_int, [H, P]),
         "lbm_destroy": (None, [H]),
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_bench_sweep": (ctypes.c_int, [H, i32, P]),
@@ -305,6 +306,12 @@ def lbm_set_state(h, f: np.ndarray) -> None:
 
 def lbm_footprint_bytes(desc: lbm_geometry_desc) -> int:
     return int(load().lbm_footprint_bytes(ctypes.byref(desc)))
+
+
+def lbm_device_bytes(h) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().lbm_device_bytes(h, ctypes.byref(n)))
+    return int(n.value)
 
 
 def lbm_destroy(h) -> None:
@@ -517,6 +524,9 @@ class Lattice:
 
     def run(self, max_steps, tol=0.0, check_every=100):
         return lbm_run_to_steady(self.h, max_steps, tol, check_every)
+
+    def device_bytes(self):
+        return lbm_device_bytes(self.h)
 
     def stats(self, flow_cap=1024):
         return lbm_outlet_stats(self.h, flow_cap)

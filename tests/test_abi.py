@@ -10,7 +10,7 @@ from paper_1303_0107_amd import lbm
 EXPECTED = {
     "lbm_create_geometry", "lbm_run_to_steady", "lbm_outlet_stats", "lbm_shape_update",
     "lbm_last_exchange", "lbm_get_mask", "lbm_get_macro", "lbm_get_state", "lbm_set_state",
-    "lbm_footprint_bytes", "lbm_destroy", "lbm_last_error", "lbm_bench_sweep",
+    "lbm_footprint_bytes", "lbm_device_bytes", "lbm_destroy", "lbm_last_error", "lbm_bench_sweep",
     "lbm_profile_sweeps", "lbm_tb_variant_count", "lbm_tb_variant_info", "lbm_tb_variant_kind",
     "lbm_set_tb_variant", "lbm_autotune", "lbm_batch_create", "lbm_batch_run",
     "lbm_batch_configure", "lbm_batch_tune", "lbm_batch_info", "lbm_batch_destroy",

@@ -192,6 +192,29 @@ def test_admission_by_footprint():
         _same(a, b)
 
 
+@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F32_S_F16])
+def test_footprint_covers_what_a_session_allocates(prec):
+    """What a served session does (create, solve, exchange steps, outlet
+    statistics) allocates no more than lbm_footprint_bytes, and not much
+    less: admission by footprint neither overcommits the device nor wastes
+    it."""
+    wl = I.HEADLINE_1024x512
+    g = lbm.Lattice(wl.types(), wl.tau, wl.u_peak, precision=prec)
+    fp = lbm.lbm_footprint_bytes(g.desc)
+    created = g.device_bytes()
+    assert 0 < created <= fp
+    g.run(300, 0.0, 100)
+    for seed in (1, 2):
+        g.shape_update(frac=0.01, seed=seed)
+        g.run(100, 0.0, 100)
+    g.stats()
+    used = g.device_bytes()
+    print(f"prec {prec}: footprint {fp} created {created} after the loop {used}", flush=True)
+    assert created <= used <= fp
+    assert used >= 0.9 * fp
+    g.close()
+
+
 def test_invalid_requests_are_refused():
     srv = lbm.Server(hbm_budget=GiB, max_sessions=2, quantum=10)
     bad = lbm.make_request(256, 128, 2, [16, 8, 4], 0.7, 0.03, lbm.LBM_F32, solve_steps=10)
