@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=1 << 28)
     ap.add_argument("--algo-bytes", type=int, default=0)
     ap.add_argument("--pmc", action="append", default=[])
+    ap.add_argument("--trace", default="",
+                    help="a --kernel-trace *_kernel_trace.csv: mean duration per kernel and grid")
     a = ap.parse_args()
     print(f"command: {a.cmd}")
     print()
@@ -104,6 +106,18 @@ def main():
     for r in csv.DictReader(open(a.stats)):
         print(f"{short(r['Name'])[:72]:72s} {int(r['Calls']):8d} {float(r['AverageNs']) / 1e3:9.3f} "
               f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.2f}")
+    if a.trace:
+        print()
+        print(f"mean duration per dispatch, by kernel and grid (threads), from {a.trace.split('/')[-1]}:")
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(a.trace)):
+            if a.kernel in r["Kernel_Name"] or a.kernel == "*":
+                g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) \
+                    if "Grid_Size_X" in r else int(r["Grid_Size"])
+                agg[(short(r["Kernel_Name"]), g)].append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        for (k, g), v in sorted(agg.items()):
+            print(f"{k[:60]:60s} grid {g:>10d} dispatches {len(v):5d} mean {sum(v) / len(v):9.3f} us")
     for path in a.pmc:
         print()
         print(f"counters per dispatch (mean) from {path.split('/')[-1]}:")
