@@ -174,7 +174,9 @@ def cpu_baseline(types, w, seconds: float):
             "mflups": mlups * nns / types.size,
             "single_thread": {"value": one, "unit": "MLUPS", "cores": 1,
                               "sample": f"{steps1} time steps ({dt1:.1f} s)"},
-            "cpu_model": cpu_model(), "host_threads": all_threads}
+            "single_thread_mflups": one * nns / types.size,
+            "cpu_model": cpu_model(), "host_threads": all_threads,
+            "nproc": os.cpu_count()}
 
 
 BATCH_WORKLOAD = "batch-256-candidates"
