@@ -209,11 +209,105 @@ __device__ __forceinline__ bool narrow_decide(Narrow &s, int lane, const Cand &c
     return true;
 }
 
+// The bin of one pass's histogram holding rank s.rr, by the 64 lanes of one
+// wave: fixes digit s.d of the bucket to it and takes the rank within it.
+// When the bin holds one candidate its index goes to *thr and s.done is set;
+// *err records an inconsistency.  Returns the bin's count (lane 0's value is
+// the one to use; every lane returns it).
+template <class Count, class Witness>
+__device__ __forceinline__ int64_t choose_bin(Narrow &s, int lane, const Cand &c, Count count,
+                                              Witness witness, int64_t *thr, int *err) {
+    unsigned hv[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        hv[q] = count(4 * lane + q);
+        sum += hv[q];
+    }
+    int64_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    const int64_t rr = s.rr;
+    int64_t base = incl - sum;
+    int found = 0, vsel = 0;
+    int64_t rnew = 0, cnt = 0;
+    if (base <= rr && rr < incl) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (base <= rr && rr < base + (int64_t)hv[q]) {
+                found = 1;
+                vsel = 4 * lane + q;
+                rnew = rr - base;
+                cnt = hv[q];
+            }
+            base += hv[q];
+        }
+    }
+    const uint64_t fm = __ballot(found);
+    if (fm == 0) {
+        if (lane == 0) {
+            *err |= 16;  // rank outside the list: unreachable
+            s.done = 1;
+        }
+        return 0;
+    }
+    const int src = __ffsll((long long)fm) - 1;
+    const int64_t bin_count = __shfl(cnt, src, 64);
+    if (lane == src) {
+        const int d = s.d, sh = 56 - 8 * (d & 7);
+        if (d < 8) {
+            s.pk |= (uint64_t)vsel << sh;
+            s.mk |= 0xffull << sh;
+        } else {
+            s.ph |= (uint64_t)vsel << sh;
+            s.mh |= 0xffull << sh;
+        }
+        s.rr = rnew;
+        if (cnt == 1) {
+            const int64_t w = witness(vsel);
+            if (w >= 0 && w < c.n) {
+                *thr = w;
+            } else {
+                *err |= 16;
+            }
+            s.done = 1;
+        }
+    }
+    return bin_count;
+}
+
+// Histogram contribution of one candidate without key ranges (all lanes of
+// the wave call this together).
+template <class AddCount, class SetWitness>
+__device__ __forceinline__ void count_candidate(bool match, uint64_t k, uint64_t h, int d,
+                                                int64_t i, AddCount add, SetWitness wit) {
+    const uint32_t v = digit(k, h, d);
+    const uint64_t mm = __ballot(match);
+    if (mm == 0) return;
+    const int first = __ffsll((long long)mm) - 1;
+    const uint32_t v0 = __shfl(v, first, 64);
+    if (__ballot(match && v == v0) == mm) {
+        if ((int)(threadIdx.x & 63) == first) {
+            add(v0, (unsigned)__popcll(mm));
+            wit(v0, i);
+        }
+    } else if (match) {
+        add(v, 1u);
+        wit(v, i);
+    }
+}
+
 // Block b finds the composite of rank r of list b (RESUME: continues the
-// select from the state the multi-block passes left, when they did not finish).  With CACHED > 0 every
-// thread keeps its (at most CACHED) candidates in registers for all the
-// passes (lists of at most CACHED * kNarrowThreads entries); otherwise each
-// pass reads the list again.
+// select from the state the multi-block passes left, when they did not
+// finish).  With CACHED > 0 every thread keeps its (at most CACHED)
+// candidates in registers for all the passes (lists of at most
+// CACHED * kNarrowThreads entries); otherwise each pass reads the list again.
+// Each pass histograms the current digit of the bucket's candidates; while
+// the digit is a key byte, a second sweep over the bucket then takes the
+// smallest and largest key of the chosen bin (one wave reduction per wave,
+// not per candidate), and the select jumps past the bytes those share.
 template <int CACHED, bool RESUME>
 __global__ __launch_bounds__(kNarrowThreads) void narrow_kernel(Cand c0, Cand c1, int64_t r,
                                                                 SelState *st) {
@@ -222,9 +316,9 @@ __global__ __launch_bounds__(kNarrowThreads) void narrow_kernel(Cand c0, Cand c1
     if (RESUME && st->nar[b].done) return;  // the passes found it: same for every thread
     __shared__ unsigned hist[256];
     __shared__ int64_t witness[256];
-    __shared__ unsigned long long kmin[256], kmax[256];
+    __shared__ unsigned long long s_lo, s_hi;
     __shared__ Narrow ns;
-    __shared__ int64_t s_thr;
+    __shared__ int64_t s_thr, s_cnt;
     __shared__ int s_err;
     if (tid == 0) {
         if (RESUME) {
@@ -250,27 +344,11 @@ __global__ __launch_bounds__(kNarrowThreads) void narrow_kernel(Cand c0, Cand c1
     }
     auto add = [&](int v, unsigned n) { atomicAdd(&hist[v], n); };
     auto wit = [&](int v, int64_t i) { witness[v] = i; };
-    auto minmax = [&](int v, uint64_t lo, uint64_t hi) {
-        atomicMin(&kmin[v], (unsigned long long)lo);
-        atomicMax(&kmax[v], (unsigned long long)hi);
-    };
-    for (int pass = 0; pass < 16; ++pass) {
-        if (tid < 256) {
-            hist[tid] = 0u;
-            witness[tid] = -1;
-            kmin[tid] = ~0ull;
-            kmax[tid] = 0ull;
-        }
-        __syncthreads();  // also publishes ns
-        const uint64_t pk = ns.pk, ph = ns.ph, mk = ns.mk, mh = ns.mh;
-        const int d = ns.d;
+    // f(key, hash, index) for every candidate of the list, all threads together
+    auto each = [&](auto &&f) {
         if (CACHED > 0) {
 #pragma unroll
-            for (int u = 0; u < NC; ++u) {
-                const int64_t i = u * kNarrowThreads + tid;
-                const bool m = i < c.n && ((ck[u] ^ pk) & mk) == 0 && ((ch[u] ^ ph) & mh) == 0;
-                bin_candidate(m, ck[u], ch[u], d, i, lane, add, wit, minmax);
-            }
+            for (int u = 0; u < NC; ++u) f(ck[u], ch[u], u * kNarrowThreads + tid);
         } else {
             // four candidates per thread per iteration (loads in flight together)
             for (int64_t base = 0; base < c.n; base += 4 * kNarrowThreads) {
@@ -282,21 +360,84 @@ __global__ __launch_bounds__(kNarrowThreads) void narrow_kernel(Cand c0, Cand c1
                     h[u] = i < c.n ? c.hash[i] : 0ull;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t i = base + u * kNarrowThreads + tid;
-                    const bool m = i < c.n && ((k[u] ^ pk) & mk) == 0 && ((h[u] ^ ph) & mh) == 0;
-                    bin_candidate(m, k[u], h[u], d, i, lane, add, wit, minmax);
-                }
+                for (int u = 0; u < 4; ++u) f(k[u], h[u], base + u * kNarrowThreads + tid);
+            }
+        }
+    };
+    for (int pass = 0; pass < 16; ++pass) {
+        if (tid < 256) {
+            hist[tid] = 0u;
+            witness[tid] = -1;
+        }
+        __syncthreads();  // also publishes ns
+        {
+            const uint64_t pk = ns.pk, ph = ns.ph, mk = ns.mk, mh = ns.mh;
+            const int d = ns.d;
+            each([&](uint64_t k, uint64_t h, int64_t i) {
+                const bool m = i < c.n && ((k ^ pk) & mk) == 0 && ((h ^ ph) & mh) == 0;
+                count_candidate(m, k, h, d, i, add, wit);
+            });
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int64_t cnt = choose_bin(
+                ns, lane, c, [&](int v) { return hist[v]; }, [&](int v) { return witness[v]; },
+                &s_thr, &s_err);
+            if (lane == 0) {
+                s_cnt = cnt;
+                s_lo = ~0ull;
+                s_hi = 0ull;
             }
         }
         __syncthreads();
-        if (tid < 64)
-            narrow_decide(
-                ns, lane, c, [&](int v) { return hist[v]; }, [&](int v) { return witness[v]; },
-                [&](int v) { return (uint64_t)kmin[v]; }, [&](int v) { return (uint64_t)kmax[v]; },
-                &s_thr, &s_err);
-        __syncthreads();
         if (ns.done) break;  // the same for every thread
+        const int d = ns.d;
+        if (d < 8) {
+            // key range of the chosen bin (the bucket with digit d fixed)
+            const uint64_t pk = ns.pk, ph = ns.ph, mk = ns.mk, mh = ns.mh;
+            uint64_t lo = ~0ull, hi = 0ull;
+            each([&](uint64_t k, uint64_t h, int64_t i) {
+                if (i < c.n && ((k ^ pk) & mk) == 0 && ((h ^ ph) & mh) == 0) {
+                    lo = min(lo, k);
+                    hi = max(hi, k);
+                }
+            });
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                lo = min(lo, (uint64_t)__shfl_xor(lo, off, 64));
+                hi = max(hi, (uint64_t)__shfl_xor(hi, off, 64));
+            }
+            if (lane == 0 && lo <= hi) {
+                atomicMin(&s_lo, (unsigned long long)lo);
+                atomicMax(&s_hi, (unsigned long long)hi);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                const uint64_t L = s_lo, H = s_hi;
+                if (L > H) {
+                    s_err |= 16;  // an empty bucket: unreachable
+                    ns.done = 1;
+                } else if (L == H) {  // every key of the bucket is L: on to the hash
+                    ns.pk = L;
+                    ns.mk = ~0ull;
+                    ns.d = 8;
+                } else {
+                    const int j = __clzll((long long)(L ^ H)) >> 3;  // first differing byte
+                    ns.pk = L & top_bytes(j);
+                    ns.mk = top_bytes(j);
+                    ns.d = j;
+                }
+            }
+        } else if (tid == 0) {
+            if (d == 15) {
+                s_err |= 1;  // composites are unique: unreachable
+                ns.done = 1;
+            } else {
+                ns.d = d + 1;
+            }
+        }
+        __syncthreads();
+        if (ns.done) break;
     }
     if (tid == 0) {
         if (s_err || !ns.done || s_thr < 0) {
