@@ -212,11 +212,10 @@ __device__ __forceinline__ bool narrow_decide(Narrow &s, int lane, const Cand &c
 // The bin of one pass's histogram holding rank s.rr, by the 64 lanes of one
 // wave: fixes digit s.d of the bucket to it and takes the rank within it.
 // When the bin holds one candidate its index goes to *thr and s.done is set;
-// *err records an inconsistency.  Returns the bin's count (lane 0's value is
-// the one to use; every lane returns it).
+// *err records an inconsistency.
 template <class Count, class Witness>
-__device__ __forceinline__ int64_t choose_bin(Narrow &s, int lane, const Cand &c, Count count,
-                                              Witness witness, int64_t *thr, int *err) {
+__device__ __forceinline__ void choose_bin(Narrow &s, int lane, const Cand &c, Count count,
+                                           Witness witness, int64_t *thr, int *err) {
     unsigned hv[4], sum = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -251,10 +250,9 @@ __device__ __forceinline__ int64_t choose_bin(Narrow &s, int lane, const Cand &c
             *err |= 16;  // rank outside the list: unreachable
             s.done = 1;
         }
-        return 0;
+        return;
     }
     const int src = __ffsll((long long)fm) - 1;
-    const int64_t bin_count = __shfl(cnt, src, 64);
     if (lane == src) {
         const int d = s.d, sh = 56 - 8 * (d & 7);
         if (d < 8) {
@@ -275,7 +273,6 @@ __device__ __forceinline__ int64_t choose_bin(Narrow &s, int lane, const Cand &c
             s.done = 1;
         }
     }
-    return bin_count;
 }
 
 // Histogram contribution of one candidate without key ranges (all lanes of
@@ -318,7 +315,7 @@ __global__ __launch_bounds__(kNarrowThreads) void narrow_kernel(Cand c0, Cand c1
     __shared__ int64_t witness[256];
     __shared__ unsigned long long s_lo, s_hi;
     __shared__ Narrow ns;
-    __shared__ int64_t s_thr, s_cnt;
+    __shared__ int64_t s_thr;
     __shared__ int s_err;
     if (tid == 0) {
         if (RESUME) {
@@ -380,11 +377,10 @@ __global__ __launch_bounds__(kNarrowThreads) void narrow_kernel(Cand c0, Cand c1
         }
         __syncthreads();
         if (tid < 64) {
-            const int64_t cnt = choose_bin(
+            choose_bin(
                 ns, lane, c, [&](int v) { return hist[v]; }, [&](int v) { return witness[v]; },
                 &s_thr, &s_err);
             if (lane == 0) {
-                s_cnt = cnt;
                 s_lo = ~0ull;
                 s_hi = 0ull;
             }
