@@ -283,6 +283,9 @@ def bench_batch(args) -> int:
             "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
         },
     }
+    hbm_and_limiter(out["roofline"], out["roofline"]["traffic"],
+                    MEASURED_VALU_PER_LAUNCH.get((BATCH_WORKLOAD, args.precision, bv, bo)),
+                    avg_ms)
     if not args.no_cpu:
         big = max(range(len(cands)), key=lambda i: types[i].size)
         out["cpu_baseline"] = cpu_baseline(types[big], cands[big], args.cpu_seconds)
@@ -447,11 +450,34 @@ MEASURED_VALU_PER_FULL_LAUNCH = {
     ("distributor-1024x512-L3", "f32", 5): 3.937e6,
     ("distributor-1024x512-L3", "f32", 1): 3.455e6,
     ("distributor-1024x512-L3", "f32", 0): 3.218e6,
+    ("distributor-1024x512-L3", "f64", 3): 5.611e6,
+    ("distributor-1024x512-L3", "f64", 1): 2.433e6,
+    ("distributor-1024x512-L3", "f64", 0): 2.240e6,
     ("channel-1024x512", "f32", 4): 8.107e6,
     ("channel-1024x512", "f32", 3): 9.306e6,
     ("channel-1024x512", "f32", 1): 15.07e6,
     ("channel-1024x512", "f32", 0): 16.11e6,
     ("channel-1024x512", "f32", 5): 19.17e6,
+    ("channel-4096x2048", "f32", 4): 125.8e6,
+    ("channel-4096x2048", "f32", 3): 146.8e6,
+    ("channel-4096x2048", "f32", 1): 235.3e6,
+    ("channel-4096x2048", "f32", 0): 256.4e6,
+    ("channel-4096x2048", "f32", 5): 296.9e6,
+}
+# The same for the batched kernel, per launch, keyed by (workload, storage,
+# shape, order) like MEASURED_TRAFFIC_PER_LAUNCH.
+MEASURED_VALU_PER_LAUNCH = {
+    ("batch-256-candidates", "f32", 4, 1): 206.5e6,
+    ("batch-256-candidates", "f32", 4, 0): 206.5e6,
+    ("batch-256-candidates", "f32", 3, 1): 199.2e6,
+    ("batch-256-candidates", "f32", 3, 0): 199.2e6,
+    ("batch-256-candidates", "f32", 2, 1): 158.7e6,
+    ("batch-256-candidates", "f32", 1, 1): 385.6e6,
+    ("batch-256-candidates", "f32", 1, 0): 385.6e6,
+    ("batch-256-candidates", "f32", 0, 1): 330.9e6,
+    ("batch-256-candidates", "f32", 0, 0): 330.9e6,
+    ("batch-256-candidates", "f32", 6, 1): 43.54e6,
+    ("batch-256-candidates", "f32", 6, 0): 43.54e6,
 }
 VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 

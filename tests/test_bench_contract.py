@@ -61,11 +61,12 @@ def test_measured_traffic_names_compiled_shapes():
         assert workload in names
         assert 0 <= shape < lbm.lbm_tb_variant_count(PREC[prec])
         assert full > 0
-    for (workload, prec, shape, order), per_launch in bench.MEASURED_TRAFFIC_PER_LAUNCH.items():
-        assert workload == bench.BATCH_WORKLOAD
-        assert 0 <= shape <= lbm.lbm_tb_variant_count(PREC[prec])  # count = one step per launch
-        assert order in (0, 1)
-        assert per_launch > 0
+    for table in (bench.MEASURED_TRAFFIC_PER_LAUNCH, bench.MEASURED_VALU_PER_LAUNCH):
+        for (workload, prec, shape, order), per_launch in table.items():
+            assert workload == bench.BATCH_WORKLOAD
+            assert 0 <= shape <= lbm.lbm_tb_variant_count(PREC[prec])  # count = one step
+            assert order in (0, 1)
+            assert per_launch > 0
 
 
 @pytest.mark.parametrize("workload", ["distributor-1024x512-L3", "channel-1024x512"])
