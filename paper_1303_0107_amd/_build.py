@@ -17,6 +17,9 @@ COMMON = [
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
+    # the leading pointer and integer arguments of each kernel (up to three)
+    # arrive preloaded in scalar registers instead of being loaded at its start
+    "-mllvm", "-amdgpu-kernarg-preload-count=3",
 ]
 # Per source: extra flags.  The double-precision sweep and the host
 # arithmetic of the reductions must not fuse multiply-adds (each IEEE

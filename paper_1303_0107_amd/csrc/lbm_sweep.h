@@ -679,10 +679,16 @@ __device__ __forceinline__ void tb_dispatch(const SweepArgs<typename Cell::T> &a
         tb_body<Cell, RH, H, NT, CHECK, BC, HALT>(a, t, steps, part_out);
 }
 
+// The tile list, the stop flag's lane copies (SweepArgs::stop) and the step
+// count come first, so that they arrive preloaded in scalar registers: the
+// tile's index and the flag are then requested at once, beside the remaining
+// arguments, instead of after them.
 template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC>
-__global__ __launch_bounds__(NT) void tb_kernel(SweepArgs<typename Cell::T> a,
-                                                const int32_t *__restrict__ tiles,
-                                                int steps) {
+__global__ __launch_bounds__(NT) void tb_kernel(const int32_t *__restrict__ tiles,
+                                                const int *__restrict__ stop, int steps,
+                                                SweepArgs<typename Cell::T> args) {
+    SweepArgs<typename Cell::T> a = args;
+    a.stop = stop;
     tb_dispatch<Cell, RH, H, NT, KIND, CHECK, BC, true>(
         a, tiles[blockIdx.x], steps, CHECK ? a.partials + (size_t)blockIdx.x * 4 : nullptr);
 }
@@ -739,7 +745,7 @@ hipError_t launch_tb_one(const SweepArgs<typename Cell::T> &a, const int32_t *ti
     static bool configured = false;  // one flag per kernel instantiation
     const hipError_t e = set_lds((const void *)k, lds, configured);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((unsigned)n_tiles), dim3(NT), lds, s, a, tiles, steps);
+    hipLaunchKernelGGL(k, dim3((unsigned)n_tiles), dim3(NT), lds, s, tiles, a.stop, steps, a);
     return hipGetLastError();
 }
 
