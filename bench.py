@@ -57,29 +57,29 @@ MEASURED_TRAFFIC_PER_FULL_LAUNCH = {
     # profiles/sweep_tb_float_distributor-1024x512.txt: shape 5 (32x64 dense
     # regions, 9 steps per launch, 236 active tiles), shape 1 (32x64 dense, 8
     # steps per launch, 234 tiles), shape 0 (32x64 compacted)
-    ("distributor-1024x512-L3", "f32", 5): 8.473e6,
-    ("distributor-1024x512-L3", "f32", 1): 8.417e6,
+    ("distributor-1024x512-L3", "f32", 5): 8.486e6,
+    ("distributor-1024x512-L3", "f32", 1): 8.403e6,
     ("distributor-1024x512-L3", "f32", 0): 8.474e6,
     # profiles/sweep_tb_double_distributor-1024x512.txt: shape 3 (32x64 in
     # place, 8 steps per launch), shape 0 (16x64 compacted, 4 steps per
     # launch), shape 1 (16x64 dense)
-    ("distributor-1024x512-L3", "f64", 3): 18.722e6,
-    ("distributor-1024x512-L3", "f64", 0): 13.145e6,
+    ("distributor-1024x512-L3", "f64", 3): 18.718e6,
+    ("distributor-1024x512-L3", "f64", 0): 13.163e6,
     ("distributor-1024x512-L3", "f64", 1): 13.133e6,
     # profiles/sweep_tb_float_channel-1024x512.txt: shape 4 (16x64 dense, 4
     # steps per launch), shape 3 (16x64 compacted), shapes 1 and 0 (32x64
     # dense and compacted, 8 steps per launch), shape 5 (32x64 dense, 9 steps)
-    ("channel-1024x512", "f32", 4): 41.018e6,
-    ("channel-1024x512", "f32", 3): 41.052e6,
-    ("channel-1024x512", "f32", 1): 43.500e6,
-    ("channel-1024x512", "f32", 0): 43.671e6,
-    ("channel-1024x512", "f32", 5): 44.356e6,
+    ("channel-1024x512", "f32", 4): 41.012e6,
+    ("channel-1024x512", "f32", 3): 41.030e6,
+    ("channel-1024x512", "f32", 1): 43.170e6,
+    ("channel-1024x512", "f32", 0): 43.250e6,
+    ("channel-1024x512", "f32", 5): 44.016e6,
     # profiles/sweep_tb_float_channel-4096x2048.txt, the same shapes
-    ("channel-4096x2048", "f32", 4): 636.576e6,
-    ("channel-4096x2048", "f32", 3): 639.227e6,
-    ("channel-4096x2048", "f32", 1): 935.988e6,
-    ("channel-4096x2048", "f32", 0): 936.232e6,
-    ("channel-4096x2048", "f32", 5): 1027.038e6,
+    ("channel-4096x2048", "f32", 4): 637.188e6,
+    ("channel-4096x2048", "f32", 3): 640.631e6,
+    ("channel-4096x2048", "f32", 1): 935.983e6,
+    ("channel-4096x2048", "f32", 0): 936.164e6,
+    ("channel-4096x2048", "f32", 5): 1027.100e6,
 }
 # The same for the batched kernel, per launch, keyed by (workload, storage,
 # shape, order).
@@ -90,18 +90,18 @@ MEASURED_TRAFFIC_PER_LAUNCH = {
     # with 9 steps per launch), 6 = one step per launch
     ("batch-256-candidates", "f32", 4, 1): 700.888e6,
     ("batch-256-candidates", "f32", 4, 0): 1366.060e6,
-    ("batch-256-candidates", "f32", 3, 1): 700.889e6,
-    ("batch-256-candidates", "f32", 3, 0): 1366.067e6,
-    ("batch-256-candidates", "f32", 2, 1): 708.367e6,
-    ("batch-256-candidates", "f32", 2, 0): 1090.893e6,
-    ("batch-256-candidates", "f32", 1, 1): 709.166e6,
-    ("batch-256-candidates", "f32", 1, 0): 1556.355e6,
-    ("batch-256-candidates", "f32", 0, 1): 709.218e6,
-    ("batch-256-candidates", "f32", 0, 0): 1556.434e6,
-    ("batch-256-candidates", "f32", 5, 1): 708.554e6,
-    ("batch-256-candidates", "f32", 5, 0): 1637.069e6,
-    ("batch-256-candidates", "f32", 6, 1): 684.541e6,
-    ("batch-256-candidates", "f32", 6, 0): 775.526e6,
+    ("batch-256-candidates", "f32", 3, 1): 700.887e6,
+    ("batch-256-candidates", "f32", 3, 0): 1366.061e6,
+    ("batch-256-candidates", "f32", 2, 1): 708.363e6,
+    ("batch-256-candidates", "f32", 2, 0): 1090.876e6,
+    ("batch-256-candidates", "f32", 1, 1): 709.157e6,
+    ("batch-256-candidates", "f32", 1, 0): 1556.352e6,
+    ("batch-256-candidates", "f32", 0, 1): 709.222e6,
+    ("batch-256-candidates", "f32", 0, 0): 1556.446e6,
+    ("batch-256-candidates", "f32", 5, 1): 708.557e6,
+    ("batch-256-candidates", "f32", 5, 0): 1637.074e6,
+    ("batch-256-candidates", "f32", 6, 1): 684.537e6,
+    ("batch-256-candidates", "f32", 6, 0): 775.521e6,
 }
 
 
