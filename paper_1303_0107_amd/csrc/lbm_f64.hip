@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbm_boundary.h"
 #include "lbm_internal.h"
 #include "lbm_keys.h"
 
@@ -170,16 +171,17 @@ __global__ __launch_bounds__(256) void mass_kernel(MacroArgs<double> a,
     if (tid == 0) partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
 }
 
-// Boundary sums in increasing y: thread k < n_out sums the x momentum of
-// outlet k; thread n_out sums x momentum and density over the inlet cells
+// Boundary sums in increasing y: workgroup k < n_out sums the x momentum of
+// outlet k; workgroup n_out sums x momentum and density over the inlet cells
 // and density over all outlet cells (one running sum each).  out layout:
 // [flow_0..flow_{n-1}, unused n, flow_in, rho_in, count_in, count_out, rho_out]
-__global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<double> a,
-                                                      const int32_t *out_y0,
-                                                      const int32_t *out_y1, int n_out,
-                                                      double *out) {
-    // One wave per task; lanes load 64 rows at once, the sums take them in
-    // increasing y one at a time (the oracle's sequential order).
+__global__ __launch_bounds__(kBoundaryThreads) void boundary_kernel(MacroArgs<double> a,
+                                                                    const int32_t *out_y0,
+                                                                    const int32_t *out_y1,
+                                                                    int n_out, double *out) {
+    // The sums take the rows in increasing y one at a time (the oracle's
+    // sequential order): an outlet's rows are read by one wave, 64 at once,
+    // the inlet and all outlet cells by the whole workgroup (boundary_ends).
     const int k = blockIdx.x, lane = threadIdx.x;
     auto at = [&](size_t n, double &r, double &mx) {
         double f[9], my;
@@ -188,6 +190,7 @@ __global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<double> a,
         moments(f, r, mx, my);
     };
     if (k < n_out) {
+        if (threadIdx.x >= 64) return;  // one wave per outlet
         const int y0 = out_y0[k], y1 = out_y1[k];
         double fl = 0.0;
         for (int c = y0; c <= y1; c += 64) {
@@ -201,42 +204,12 @@ __global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<double> a,
             out[n_out + k] = 0.0;
         }
     } else {
-        double fl = 0.0, rin = 0.0, rout = 0.0, cin = 0.0, cout = 0.0;
-        for (int c = 0; c < a.ny; c += 64) {
-            const int y = c + lane;
-            double ro = 0.0, ri = 0.0, mi = 0.0, mo;
-            int is_out = 0, is_in = 0;
-            if (y < a.ny) {
-                const size_t n0 = (size_t)y * a.pitch;
-                if (cell_type(a.cell[n0 + a.nx - 1]) == kOutlet) {
-                    at(n0 + a.nx - 1, ro, mo);
-                    is_out = 1;
-                }
-                if (cell_type(a.cell[n0]) == kInlet) {
-                    at(n0, ri, mi);
-                    is_in = 1;
-                }
-            }
-            const int m = min(64, a.ny - c);
-            for (int t = 0; t < m; ++t) {
-                if (__shfl(is_out, t, 64)) {
-                    rout += __shfl(ro, t, 64);
-                    cout += 1.0;
-                }
-                if (__shfl(is_in, t, 64)) {
-                    fl += __shfl(mi, t, 64);
-                    rin += __shfl(ri, t, 64);
-                    cin += 1.0;
-                }
-            }
-        }
-        if (lane == 0) {
-            out[2 * n_out + 0] = fl;
-            out[2 * n_out + 1] = rin;
-            out[2 * n_out + 2] = cin;
-            out[2 * n_out + 3] = cout;
-            out[2 * n_out + 4] = rout;
-        }
+        double o[5];
+        boundary_ends(a.cell, a.nx, a.ny, a.pitch,
+                      [&](size_t n, double &r, double &mx) { at(n, r, mx); }, o);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) out[2 * n_out + q] = o[q];
     }
 }
 
@@ -337,8 +310,8 @@ template <>
 hipError_t launch_boundary<double>(const MacroArgs<double> &a, const int32_t *y0,
                                    const int32_t *y1, int n_out, double *out,
                                    hipStream_t s) {
-    hipLaunchKernelGGL(f64::boundary_kernel, dim3((unsigned)(n_out + 1)), dim3(64), 0, s, a, y0,
-                       y1, n_out, out);
+    hipLaunchKernelGGL(f64::boundary_kernel, dim3((unsigned)(n_out + 1)), dim3(kBoundaryThreads),
+                       0, s, a, y0, y1, n_out, out);
     return hipGetLastError();
 }
 

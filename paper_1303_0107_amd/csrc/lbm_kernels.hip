@@ -24,6 +24,7 @@
 
 #include <cstring>
 
+#include "lbm_boundary.h"
 #include "lbm_internal.h"
 #include "lbm_keys.h"
 #include "lbm_sweep.h"
@@ -329,18 +330,20 @@ __global__ __launch_bounds__(256) void mass_kernel(MacroArgs<T> a,
     if (tid == 0) partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = v[0];
 }
 
-// Boundary sums (Sec. 4.2) in increasing y: thread k < n_out sums rho u_x
-// and rho over outlet k's rows y0..y1 (column nx-1); thread n_out sums over
-// the inlet cells of column 0 and the density over all outlet cells.  out:
+// Boundary sums (Sec. 4.2) in increasing y: workgroup k < n_out sums rho u_x
+// and rho over outlet k's rows y0..y1 (column nx-1); workgroup n_out sums
+// over the inlet cells of column 0 and the density over all outlet cells.  out:
 // [flow_0..flow_{n-1}, rho_0..rho_{n-1}, flow_in, rho_in, count_in,
 //  count_out, rho_out]
 template <typename T>
-__global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<T> a, const int32_t *out_y0,
-                                                      const int32_t *out_y1, int n_out,
-                                                      double *out) {
-    // One wave per task (outlet k, or k = n_out: inlet and all outlet cells).
-    // Lanes load 64 rows at once; the sums then take them in increasing y,
-    // one row at a time, so every sum has the order of a sequential loop.
+__global__ __launch_bounds__(kBoundaryThreads) void boundary_kernel(MacroArgs<T> a,
+                                                                    const int32_t *out_y0,
+                                                                    const int32_t *out_y1,
+                                                                    int n_out, double *out) {
+    // Workgroup k < n_out: outlet k, one wave (the others leave), its rows
+    // read 64 at once; workgroup n_out: the inlet and all outlet cells
+    // (boundary_ends).  The sums take the rows in increasing y, one row at a
+    // time, so every sum has the order of a sequential loop.
     const int k = blockIdx.x, lane = threadIdx.x;
     auto moments = [&](size_t n, double &rho, double &jx) {
         double d[9];
@@ -351,6 +354,7 @@ __global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<T> a, const int3
         rho = 1.0 + dr;
     };
     if (k < n_out) {
+        if (threadIdx.x >= 64) return;  // one wave per outlet
         const int y0 = out_y0[k], y1 = out_y1[k];
         double fl = 0.0, rs = 0.0;
         for (int c = y0; c <= y1; c += 64) {
@@ -367,42 +371,12 @@ __global__ __launch_bounds__(64) void boundary_kernel(MacroArgs<T> a, const int3
             out[n_out + k] = rs;
         }
     } else {
-        double fl = 0.0, rs = 0.0, cnt = 0.0, cnt_out = 0.0, rout = 0.0;
-        for (int c = 0; c < a.ny; c += 64) {
-            const int y = c + lane;
-            double ro = 0.0, ri = 0.0, ji = 0.0, jo;
-            int is_out = 0, is_in = 0;
-            if (y < a.ny) {
-                const size_t n = (size_t)y * a.pitch;
-                if (cell_type(a.cell[n + a.nx - 1]) == kOutlet) {
-                    moments(n + a.nx - 1, ro, jo);
-                    is_out = 1;
-                }
-                if (cell_type(a.cell[n]) == kInlet) {
-                    moments(n, ri, ji);
-                    is_in = 1;
-                }
-            }
-            const int m = min(64, a.ny - c);
-            for (int t = 0; t < m; ++t) {  // the same order as a loop over y
-                if (__shfl(is_out, t, 64)) {
-                    rout += __shfl(ro, t, 64);
-                    cnt_out += 1.0;
-                }
-                if (__shfl(is_in, t, 64)) {
-                    fl += __shfl(ji, t, 64);
-                    rs += __shfl(ri, t, 64);
-                    cnt += 1.0;
-                }
-            }
-        }
-        if (lane == 0) {
-            out[2 * n_out + 0] = fl;
-            out[2 * n_out + 1] = rs;
-            out[2 * n_out + 2] = cnt;
-            out[2 * n_out + 3] = cnt_out;
-            out[2 * n_out + 4] = rout;
-        }
+        double o[5];
+        boundary_ends(a.cell, a.nx, a.ny, a.pitch,
+                      [&](size_t n, double &rho, double &jx) { moments(n, rho, jx); }, o);
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) out[2 * n_out + q] = o[q];
     }
 }
 
@@ -594,8 +568,8 @@ template <typename T>
 hipError_t launch_boundary(const MacroArgs<T> &a, const int32_t *y0,
                            const int32_t *y1, int n_out, double *out,
                            hipStream_t s) {
-    hipLaunchKernelGGL(boundary_kernel<T>, dim3((unsigned)(n_out + 1)), dim3(64), 0, s, a, y0,
-                       y1, n_out, out);
+    hipLaunchKernelGGL(boundary_kernel<T>, dim3((unsigned)(n_out + 1)), dim3(kBoundaryThreads),
+                       0, s, a, y0, y1, n_out, out);
     return hipGetLastError();
 }
 
