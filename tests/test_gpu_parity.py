@@ -297,6 +297,25 @@ def test_ragged_multi_tile_window(prec):
     assert stats_ok(g, o, tol, f"ragged 200x70 prec={prec}")[0]
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_boundary_sums_over_several_row_spans(prec):
+    """A tall channel, 2500 rows: the inlet-and-outlets sums take two full
+    spans of 1024 rows and a ragged one.  Every sum keeps the row order, so
+    FP64 fluxes, inlet flux and pressure drop equal the oracle's bit for bit;
+    FP32 within its tolerance."""
+    t = I.channel(40, 2500)
+    g = lbm.Lattice(t, 0.7, 0.03, precision=prec)
+    o = oracle.Lattice(t, 0.7, 0.03)
+    g.run(60, 0.0, 100)
+    o.run(60, 0.0, 100)
+    ok, sg, so = stats_ok(g, o, TOL[prec], f"tall channel 40x2500 prec={prec}")
+    assert ok
+    if prec == lbm.LBM_F64:
+        flow, sg = g.stats()
+        assert np.array_equal(flow, so.flow) and sg.dp == so.dp and sg.flow_in == so.flow_in
+    g.close()
+
+
 def test_run_to_steady_matches_oracle_f64():
     wl = I.CORRECTNESS_128x64
     t = wl.types()
