@@ -7,6 +7,16 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# Under pytest-xdist every worker loads its own OpenMP oracle.  With one
+# thread per core in each worker the cores are oversubscribed, and OpenMP's
+# spinning barriers (one per pass of every time step) then stall for whole
+# scheduler slices: a 0.3 s test took over two minutes with two workers.
+# Each worker gets an equal share of the cores instead (before the oracle's
+# runtime reads the setting), unless the caller chose a thread count.
+if os.environ.get("PYTEST_XDIST_WORKER") and "OMP_NUM_THREADS" not in os.environ:
+    workers = max(1, int(os.environ.get("PYTEST_XDIST_WORKER_COUNT", "1")))
+    os.environ["OMP_NUM_THREADS"] = str(max(1, (os.cpu_count() or 1) // workers))
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
