@@ -228,14 +228,13 @@ struct RunControl {
     int stop_lanes[64];  // copies of stop, one per lane (SweepArgs::stop)
     int zeros[64];       // SweepArgs::stop outside a queued run
 };
-// Sums of interval j into ctl->sums[j] (same order as launch_finalize4), then
+// Sums of interval j into ctl->sums[j] (thread t < 256 adds partials t,
+// t + 256, ..., then the block adds the threads' sums in a fixed order), then
 // the stop decision: unstable if sums[3] != 0 or a sum is not finite, else
 // converged if tol > 0 and sqrt(num)/sqrt(den) < tol.  Does nothing once
 // ctl->stop is set.
 hipError_t launch_finalize_check(const double *partials, int64_t count, RunControl *ctl, int j,
                                  double tol, hipStream_t s);
-hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
-                            hipStream_t s);
 hipError_t launch_finalize1(const double *partials, int64_t count, double *out,
                             hipStream_t s);
 template <typename T>

@@ -529,13 +529,6 @@ int64_t sweep_blocks(int nx, int ny) {
     return (int64_t)g.x * g.y;
 }
 
-hipError_t launch_finalize4(const double *partials, int64_t count, double *out,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel<4>, dim3(1), dim3(256), 0, s, partials,
-                       count, out);
-    return hipGetLastError();
-}
-
 hipError_t launch_finalize_check(const double *partials, int64_t count, RunControl *ctl, int j,
                                  double tol, hipStream_t s) {
     hipLaunchKernelGGL(finalize_check_kernel, dim3(1), dim3(256), 0, s, partials, count, ctl, j,
