@@ -584,6 +584,8 @@ def optimise_leg(args, w, prec_name: str, copy_gbs: float):
                            f"{halo} steps per launch)",
         "bytes_per_step": bytes_per_step, "steps_per_launch": round(steps_per_launch, 3),
         "bytes_per_launch": round(bytes_per_launch), "launches": launches,
+        "launch_timing": "HIP events on the handle's stream around the launches of every "
+                         "4th check interval of the timed solves",
         "avg_launch_us": round(avg_ms * 1e3, 3),
         "copy_ceiling_GBs": round(copy_gbs, 1),
         "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),

@@ -316,10 +316,13 @@ const char *lbm_last_error(void);
 int lbm_bench_sweep(lbm_handle *h, int32_t steps, double *ms_per_step);
 
 /* Sweep timing inside lbm_run_to_steady.  enable = 1 resets the counters
- * and starts recording: each residual-check interval then records a HIP
- * event on the handle's stream before its first sweep launch and after its
- * last one, and adds the elapsed time, the time steps and the sweep kernel
- * launches in between (a launch may advance several steps).  enable = 0
+ * and starts recording: every fourth residual-check interval (the first of
+ * each four counted since enabling) then records a HIP event on the
+ * handle's stream before its first sweep launch and after its last one, and
+ * adds the elapsed time, the time steps and the sweep kernel launches in
+ * between (a launch may advance several steps); the totals cover those
+ * intervals only.  Recording every interval slowed the run itself by a few
+ * per cent (two stream markers per interval).  enable = 0
  * stops recording.  Either way the current totals are returned (any of
  * steps, launches, total_ms may be NULL). */
 int lbm_profile_sweeps(lbm_handle *h, int32_t enable, int64_t *steps,
