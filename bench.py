@@ -710,7 +710,7 @@ def main() -> int:
                     help="arrival window of the serving leg of the default run")
     ap.add_argument("--hbm-budget-gb", type=float, default=32.0)
     ap.add_argument("--max-sessions", type=int, default=64)
-    ap.add_argument("--quantum", type=int, default=20)
+    ap.add_argument("--quantum", type=int, default=40)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -455,7 +455,7 @@ def make_request(nx, ny, levels, widths, tau, u_peak, precision=LBM_F32, kind=LB
 class Server:
     """Owning wrapper of a request server (worker thread in the library)."""
 
-    def __init__(self, hbm_budget: int, max_sessions: int = 64, quantum: int = 20,
+    def __init__(self, hbm_budget: int, max_sessions: int = 64, quantum: int = 40,
                  variant: int = -1, order: int = 1, stream=None):
         cfg = lbm_server_config(int(hbm_budget), int(max_sessions), int(quantum), int(variant),
                                 int(order))
