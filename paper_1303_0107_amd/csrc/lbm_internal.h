@@ -220,7 +220,7 @@ constexpr int kNoAllocMaxOutlets = 1024;
 // are queued several at a time, and each interval's finalize step records the
 // interval's sums, counts it, and ends the run (stop = 1 converged, 2
 // unstable) so that the launches queued after it change nothing.
-constexpr int kRunBatchMax = 16;
+constexpr int kRunBatchMax = 64;
 struct RunControl {
     double sums[kRunBatchMax][4];
     int stop;
