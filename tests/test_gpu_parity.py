@@ -764,6 +764,23 @@ def test_bitwise_deterministic():
     assert np.array_equal(out[0][2], out[1][2])
 
 
+def test_run_timing_covers_every_fourth_interval():
+    """Sweep timing inside a run (the benchmark's launch time) records the
+    first of every four check intervals since it was enabled: over ten
+    intervals of 100 steps, intervals 0, 4 and 8, with their launches."""
+    wl = I.CORRECTNESS_128x64
+    g = lbm.Lattice(wl.types(), wl.tau, wl.u_peak, precision=lbm.LBM_F32)
+    v = lbm.lbm_get_tb_variant(g.h)
+    per_interval = -(-100 // lbm.lbm_tb_variant_info(lbm.LBM_F32, v)[1]) if v >= 0 else 100
+    g.profile_sweeps(True)
+    rc, n, _ = g.run(1000, 0.0, 100)
+    steps, launches, ms = g.profile_sweeps(False)
+    report("run timing", variant=v, steps=steps, launches=launches, ms=ms)
+    assert rc == lbm.LBM_OK and n == 1000
+    assert steps == 300 and launches == 3 * per_interval and ms > 0.0
+    g.close()
+
+
 @pytest.mark.parametrize("prec,tol", [(lbm.LBM_F64, 1e-7), (lbm.LBM_F32, 3e-6)])
 def test_queued_check_intervals_stop_where_one_interval_at_a_time_stops(prec, tol):
     """A run to steady state queues several check intervals and lets the
