@@ -330,6 +330,16 @@ struct lbm_handle {
     DeviceBuffer cell, types, uin, uprev, partials, red, out_rows, bnd;
     DeviceBuffer ctl;                    // RunControl of lbm_run_to_steady
     const int *active_stop = nullptr;    // its stop flag while a run is queued
+    // While a blocked run is queued: the check launch of the interval being
+    // queued writes its partials at run_part, and, when run_prev is set, the
+    // interval's first launch carries out the finalize step of interval
+    // run_j - 1 from run_prev (SweepArgs::prev) and writes the stop flag to
+    // run_stop_rest, which the interval's later launches read.
+    double *run_part = nullptr;
+    const double *run_prev = nullptr;
+    int *run_stop_rest = nullptr;
+    int run_j = 0;
+    double run_tol = 0.0;
     hipEvent_t run_ev[2 * kRunBatchMax] = {};  // per-interval timing of a run
     DeviceBuffer macro;  // 3*nx*ny doubles (rho, ux, uy), on demand
     DeviceBuffer cand, sel, select_tmp;
@@ -465,6 +475,12 @@ size_t max_tile_count(int nx, int ny, int precision) {
     return m;
 }
 
+// Partial slots of a lattice (4 doubles each): one per sweep block, or two
+// per tile (a queued run alternates between two halves of the buffer).
+size_t partial_slots(int nx, int ny, int precision) {
+    return std::max((size_t)sweep_blocks(nx, ny), 2 * max_tile_count(nx, ny, precision));
+}
+
 // Initial capacity of each exchange-step candidate list.
 int64_t initial_cand_cap(size_t N) { return std::max<int64_t>(4096, (int64_t)(N / 16)); }
 
@@ -480,7 +496,7 @@ size_t footprint(int nx, int ny, int precision) {
     b += c((size_t)ny * sizeof(double));     // inlet profile
     b += c(2 * plane * sizeof(double));      // u_prev
     const size_t ntiles = max_tile_count(nx, ny, precision);
-    b += c(std::max((size_t)sweep_blocks(nx, ny), ntiles) * 4 * sizeof(double));
+    b += c(partial_slots(nx, ny, precision) * 4 * sizeof(double));
     b += c(ntiles * sizeof(int32_t));
     // exchange step, allocated on the first one: the two candidate lists at
     // their initial capacity, the selection scratch and the selections (each
@@ -660,7 +676,7 @@ SweepArgs<T> sweep_args(lbm_handle *h, bool check) {
     a.cell = h->cell.as<uint16_t>();
     a.uin = h->uin.as<UinT<T>>();
     a.uprev = check ? h->uprev.as<double>() : nullptr;
-    a.partials = check ? h->partials.as<double>() : nullptr;
+    a.partials = !check ? nullptr : h->run_part ? h->run_part : h->partials.as<double>();
     a.stop = !h->use_tb ? nullptr
              : h->active_stop ? h->active_stop
                               : h->ctl.as<RunControl>()->zeros;
@@ -746,12 +762,25 @@ void plain_sweeps(lbm_handle *h, int64_t n) {
 template <typename T>
 void advance(lbm_handle *h, int64_t n, bool check) {
     if (h->use_tb) {
+        bool first = true;
         while (n > 0) {
             const int s =
                 (int)std::min<int64_t>(n, steps_per_launch(h->precision, h->tb_variant));
             n -= s;
-            HIP_TRY(launch_tb<T>(sweep_args<T>(h, check && n == 0), h->tiles.as<int32_t>(),
-                                 h->n_tiles, s, check && n == 0, h->tb_variant, h->stream));
+            SweepArgs<T> a = sweep_args<T>(h, check && n == 0);
+            if (first && h->run_prev) {
+                a.prev = h->run_prev;
+                a.stop_out = h->run_stop_rest;
+                a.ctl = h->ctl.as<RunControl>();
+                a.prev_j = h->run_j - 1;
+                a.prev_count = h->n_tiles;
+                a.tol = h->run_tol;
+            } else if (!first && h->run_stop_rest) {
+                a.stop = h->run_stop_rest;
+            }
+            first = false;
+            HIP_TRY(launch_tb<T>(a, h->tiles.as<int32_t>(), h->n_tiles, s, check && n == 0,
+                                 h->tb_variant, h->stream));
             h->cur = 1 - h->cur;
             ++h->prof_kernels;
         }
@@ -806,14 +835,30 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
     // goes on, the launches queued after the deciding one change nothing, and
     // the host waits once per batch instead of once per interval.  The batch
     // grows while the residual is far from the tolerance and shrinks near it.
+    // On a lattice of at most kDeferMaxPartials tiles the finalize step of
+    // each interval but a batch's last is carried out by the next interval's
+    // first launch when that is not also its check launch (the partials
+    // alternate between two halves of the buffer), the others by a launch of
+    // their own.
     h->ctl.ensure(sizeof(RunControl));
     RunControl *ctl = h->ctl.as<RunControl>();
     HIP_TRY(hipMemsetAsync(ctl, 0, sizeof(RunControl), h->stream));
     struct ActiveStop {  // the stop flag reaches the launches of this run only
         lbm_handle *h;
-        ~ActiveStop() { h->active_stop = nullptr; }
+        ~ActiveStop() {
+            h->active_stop = nullptr;
+            h->run_part = nullptr;
+            h->run_prev = nullptr;
+            h->run_stop_rest = nullptr;
+        }
     } guard{h};
-    h->active_stop = h->use_tb ? ctl->stop_lanes : nullptr;
+    const char *no_defer = std::getenv("LBM_DEFER");  // "0": a finalize launch per interval
+    const bool defer = h->use_tb && h->n_tiles > 0 && h->n_tiles <= kDeferMaxPartials &&
+                       !(no_defer && no_defer[0] == '0');
+    double *const part = h->partials.as<double>();
+    auto half = [&](int j) { return defer ? part + (size_t)(j % 2) * h->n_tiles * 4 : part; };
+    h->run_tol = tol;
+    h->active_stop = h->use_tb ? ctl->stop_lanes[0] : nullptr;
     // Timing-only events: without the system-scope fence that an ordinary
     // event record adds (a cache writeback and invalidation between two
     // launches), which cost 4.7 % of the headline solve's time at two
@@ -838,16 +883,37 @@ int run_impl(lbm_handle *h, int64_t max_steps, double tol, int32_t k,
             at += chunk[planned];
             const int64_t k0 = h->prof_kernels;
             timed[planned] = h->profiling && h->prof_intervals++ % kProfileEvery == 0;
+            // an interval of one launch (its check launch) leaves the finalize
+            // step of the interval before it to a launch of its own
+            const bool by_first = defer && planned > 0 &&
+                                  chunk[planned] > steps_per_launch(h->precision, h->tb_variant);
+            if (defer && planned > 0 && !by_first)
+                HIP_TRY(launch_finalize_check(half(planned - 1), nparts, ctl, planned - 1, tol,
+                                              h->stream));
+            h->run_j = planned;
+            h->run_part = half(planned);
+            h->run_prev = by_first ? half(planned - 1) : nullptr;
+            if (h->use_tb) {
+                h->active_stop = ctl->stop_lanes[planned % 2];
+                h->run_stop_rest = ctl->stop_lanes[(planned + (by_first ? 1 : 0)) % 2];
+            }
             if (timed[planned]) HIP_TRY(hipEventRecord(h->run_ev[2 * planned], h->stream));
             advance<T>(h, chunk[planned], true);
             if (timed[planned])
                 HIP_TRY(hipEventRecord(h->run_ev[2 * planned + 1], h->stream));
             kernels[planned] = h->prof_kernels - k0;
             h->prof_kernels = k0;
-            HIP_TRY(launch_finalize_check(h->partials.as<double>(), nparts, ctl, planned, tol,
-                                          h->stream));
+            if (!defer)
+                HIP_TRY(launch_finalize_check(half(planned), nparts, ctl, planned, tol,
+                                              h->stream));
             cur_after[planned] = h->cur;
         }
+        h->run_part = nullptr;
+        h->run_prev = nullptr;
+        h->run_stop_rest = nullptr;
+        if (defer)
+            HIP_TRY(launch_finalize_check(half(planned - 1), nparts, ctl, planned - 1, tol,
+                                          h->stream));
         const RunControl *rc = reinterpret_cast<const RunControl *>(h->pinned);
         HIP_TRY(hipMemcpyAsync(h->pinned, ctl, sizeof(RunControl), hipMemcpyDeviceToHost,
                                h->stream));
@@ -1318,9 +1384,7 @@ int lbm_create_geometry(const lbm_geometry_desc *d, const uint8_t *cell_types,
         h->types.ensure(h->N());
         h->uin.ensure((size_t)h->ny * sizeof(double));
         h->uprev.ensure(2 * h->plane * sizeof(double));
-        const size_t ntiles = max_tile_count(h->nx, h->ny, h->precision);
-        h->partials.ensure(std::max((size_t)sweep_blocks(h->nx, h->ny), ntiles) * 4 *
-                           sizeof(double));
+        h->partials.ensure(partial_slots(h->nx, h->ny, h->precision) * 4 * sizeof(double));
         h->red.ensure(64 * sizeof(double));
         h->ctl.ensure(sizeof(RunControl));
         HIP_TRY(hipMemsetAsync(h->ctl.p, 0, sizeof(RunControl), h->stream));

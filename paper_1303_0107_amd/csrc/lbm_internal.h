@@ -103,6 +103,11 @@ using UinT = typename std::conditional<std::is_same<T, double>::value, double, f
 template <typename T>
 using ArithT = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
 
+struct RunControl;
+// Queued runs on lattices of at most this many tiles let the first launch of
+// each interval carry out the finalize step of the interval before it.
+constexpr int kDeferMaxPartials = 512;
+
 template <typename T>
 struct SweepArgs {
     const T *fin;
@@ -122,6 +127,18 @@ struct SweepArgs {
     double rho_out;
     double one_minus_rho_out;
     int flags;         // kFlagNeumannOutlet | kFlagSymmetryTop
+    // Set on the first launch of interval j >= 1 of a queued run when the
+    // tile list holds at most kDeferMaxPartials tiles and that launch is not
+    // the interval's check launch (single-lattice blocked kernels, a kernel
+    // of its own): the launch first carries out the finalize step of
+    // interval prev_j = j - 1 (RunControl) from that interval's prev_count
+    // partials with tolerance tol, and writes the stop flag's lane copies to
+    // stop_out, in place of a finalize launch.  Null otherwise.
+    const double *prev = nullptr;
+    int *stop_out = nullptr;
+    RunControl *ctl = nullptr;
+    int prev_j = 0, prev_count = 0;
+    double tol = 0.0;
 };
 
 template <typename T>
@@ -225,7 +242,13 @@ struct RunControl {
     double sums[kRunBatchMax][4];
     int stop;
     int done;            // intervals of the current batch carried out
-    int stop_lanes[64];  // copies of stop, one per lane (SweepArgs::stop)
+    // Copies of stop, one per lane (SweepArgs::stop), in two arrays: the
+    // launches of interval j read [j % 2], except those after the first
+    // launch of an interval whose first launch decides the interval before
+    // it (SweepArgs::prev): that launch writes the decision to [(j + 1) % 2],
+    // which the rest of the interval reads, so that no launch writes an array
+    // it reads.  A finalize launch writes both.
+    int stop_lanes[2][64];
     int zeros[64];       // SweepArgs::stop outside a queued run
 };
 // Sums of interval j into ctl->sums[j] (thread t < 256 adds partials t,

@@ -263,23 +263,9 @@ __global__ __launch_bounds__(256) void finalize_check_kernel(const double *parti
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] += partials[i * 4 + k];
     block_sum<4>(v, threadIdx.x, 256);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) ctl->sums[j][k] = v[k];
-        ctl->done = j + 1;
-        const double num = v[0], den = v[1], bad = v[3];
-        int stop = 0;
-        if (bad != 0.0 || !isfinite(num) || !isfinite(den)) {
-            stop = 2;
-        } else if (tol > 0.0) {
-            const double r = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : sqrt(num) / sqrt(den);
-            if (r < tol) stop = 1;
-        }
-        if (stop) {
-            ctl->stop = stop;
-            for (int l = 0; l < 64; ++l) ctl->stop_lanes[l] = stop;
-        }
-    }
+    if (threadIdx.x == 0)
+        sweep::record_interval(ctl, j, v, sweep::interval_stop(v, tol), ctl->stop_lanes[0],
+                               ctl->stop_lanes[1]);
 }
 
 // ---------------------------------------------------------------------------

@@ -121,6 +121,120 @@ __device__ __forceinline__ void block_sum(double (&v)[NV]) {
     }
 }
 
+// Stop decision of a check interval from its four sums (residual numerator
+// and denominator, mass, non-finite count): 2 when the run became unstable
+// (a non-finite sum, or a non-finite cell flagged), 1 when it converged (tol
+// > 0 and sqrt(num)/sqrt(den) < tol), else 0.
+__device__ __forceinline__ int interval_stop(const double (&v)[4], double tol) {
+    const double num = v[0], den = v[1], bad = v[3];
+    if (bad != 0.0 || !isfinite(num) || !isfinite(den)) return 2;
+    if (tol > 0.0) {
+        const double r = den == 0.0 ? (num == 0.0 ? 0.0 : INFINITY) : sqrt(num) / sqrt(den);
+        if (r < tol) return 1;
+    }
+    return 0;
+}
+
+// Records interval j of a queued run (one thread): its sums, the count of
+// intervals carried out, and the stop flag, with its lane copies in lanes0
+// and, if given, lanes1.
+__device__ __forceinline__ void record_interval(RunControl *ctl, int j, const double (&v)[4],
+                                                int stop, int *lanes0, int *lanes1) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ctl->sums[j][k] = v[k];
+    ctl->done = j + 1;
+    if (stop) {
+        ctl->stop = stop;
+        for (int l = 0; l < 64; ++l) {
+            lanes0[l] = stop;
+            if (lanes1) lanes1[l] = stop;
+        }
+    }
+}
+
+// Start of a blocked launch that may belong to a queued run (HALT).  The
+// run's stop flag and, on the first launch of an interval that decides the
+// interval before it (PREV, SweepArgs::prev), that interval's partials are
+// read at the start, beside the region.  The workgroup leaves before its
+// first barrier when the run had already ended, and right after it when the
+// previous interval ends the run; no global store precedes either exit.
+// The previous interval is summed in finalize_check_kernel's order (threads
+// 0-255 add partials t and t + 256, the waves add their lanes, then the four
+// wave sums are added in wave order), so every workgroup reaches the sums,
+// bit for bit, that a finalize launch would record; workgroup 0 records
+// them and writes the stop flag (the decision, or the flag it read) to the
+// lane copies the interval's later launches read (SweepArgs::stop_out).
+template <int NT, bool HALT, bool PREV>
+struct RunGate {
+    static_assert(!PREV || NT >= 256, "the previous interval's sum order takes 256 threads");
+    int halt = 0;
+    double p[2][4];
+
+    template <typename T>
+    __device__ __forceinline__ void read(const SweepArgs<T> &a) {
+        if (!HALT) return;
+        halt = a.stop[threadIdx.x & 63];
+        if (!PREV) return;
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const bool in = t < 256 && t + 256 * r < a.prev_count;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) p[r][k] = in ? a.prev[(size_t)(t + 256 * r) * 4 + k] : 0.0;
+        }
+    }
+
+    static __device__ __forceinline__ double (*wave_sums())[4] {
+        __shared__ double s[4][4];
+        return s;
+    }
+
+    // Before the first barrier: true when the run had already ended (the
+    // flag is the same for every lane).
+    template <typename T>
+    __device__ __forceinline__ bool ended(const SweepArgs<T> &a) {
+        if (!HALT) return false;
+        const int t = threadIdx.x;
+        if (__builtin_amdgcn_readfirstlane(halt)) {
+            if (PREV && blockIdx.x == 0 && t < 64) a.stop_out[t] = halt;  // passed on
+            return true;
+        }
+        if (PREV && t < 256) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                if (t + 256 * r < a.prev_count)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) v[k] += p[r][k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], off, 64);
+            if ((t & 63) == 0)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) wave_sums()[t >> 6][k] = v[k];
+        }
+        return false;
+    }
+
+    // After the first barrier: true when the previous interval ends the run.
+    template <typename T>
+    __device__ __forceinline__ bool ends_now(const SweepArgs<T> &a) {
+        if (!HALT || !PREV) return false;
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double s = wave_sums()[0][k];
+            for (int w = 1; w < 4; ++w) s += wave_sums()[w][k];
+            v[k] = s;
+        }
+        const int stop = interval_stop(v, a.tol);
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            record_interval(a.ctl, a.prev_j, v, stop, a.stop_out, nullptr);
+        return stop != 0;
+    }
+};
+
 // Residual terms of one cell (|u - u_prev|^2, |u|^2, rho, non-finite count)
 // added to `part`; u_prev is replaced by u.
 template <typename T>
@@ -221,7 +335,7 @@ __global__ __launch_bounds__(256) void step_batch_kernel(
 // distance to the region edge; 0 for solid cells) bounds the steps it can
 // take: it is advanced at step s exactly when depth >= s, and is a tile cell
 // exactly when depth >= H.
-template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT>
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT, bool PREV>
 __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, const int t,
                                         const int steps, double *part_out) {
     using T = typename Cell::T;
@@ -235,7 +349,8 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int halt = HALT ? a.stop[lane] : 0;  // vector load beside the region's
+    RunGate<NT, HALT, PREV> gate;
+    gate.read(a);  // beside the region's loads
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
 
@@ -283,10 +398,9 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
         }
         dst[c].set(L, pos);
     }
-    // the whole workgroup leaves when the run has ended (the flag, read with
-    // the region, is the same for every lane)
-    if (HALT && __builtin_amdgcn_readfirstlane(halt)) return;
+    if (gate.ended(a)) return;
     __syncthreads();
+    if (gate.ends_now(a)) return;
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     // One step reading copy B and writing copy 1 - B; true when it was the last.
@@ -353,7 +467,7 @@ __device__ __forceinline__ void tb_body(const SweepArgs<typename Cell::T> &a, co
 // as tall fit (FP64 64 x 32: 147 KB).  Cells, depths and the order of the
 // arithmetic are those of the two-copy form, so the results are the same
 // bits.
-template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT>
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT, bool PREV>
 __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T> &a,
                                                 const int t, const int steps,
                                                 double *part_out) {
@@ -367,7 +481,8 @@ __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int halt = HALT ? a.stop[lane] : 0;  // vector load beside the region's
+    RunGate<NT, HALT, PREV> gate;
+    gate.read(a);  // beside the region's loads
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
 
@@ -403,10 +518,9 @@ __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T
     for (int c = 0; c < CPT; ++c)
 #pragma unroll
         for (int i = 0; i < 9; ++i) L[i * PL + (wave + c * NW) * RW + lane] = v[c][i];
-    // the whole workgroup leaves when the run has ended (the flag, read with
-    // the region, is the same for every lane)
-    if (HALT && __builtin_amdgcn_readfirstlane(halt)) return;
+    if (gate.ended(a)) return;
     __syncthreads();
+    if (gate.ends_now(a)) return;
 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     // Pulls of one cell (its nine populations after streaming, and for a
@@ -486,7 +600,7 @@ __device__ __forceinline__ void tb_body_inplace(const SweepArgs<typename Cell::T
 // Each update reads the same nine values as the dense form, so the results
 // are the same bits.  LDS: the two region copies, interleaved by plane as in
 // the dense form, then PL list words.
-template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT>
+template <class Cell, int RH, int H, int NT, bool CHECK, bool BC, bool HALT, bool PREV>
 __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T> &a, const int t,
                                                 const int steps, double *part_out) {
     using T = typename Cell::T;
@@ -504,7 +618,8 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
 
     const int ox = (t & 0xffff) * IW - H, oy = (t >> 16) * IH - H;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int halt = HALT ? a.stop[lane] : 0;  // vector load beside the region's
+    RunGate<NT, HALT, PREV> gate;
+    gate.read(a);  // beside the region's loads
     const int gx = ox + lane;
     const bool col_in = gx >= 0 && gx < a.nx;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -547,10 +662,9 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
             if (lane == 0) row_off[ry][k - 1] = __popcll(m);
         }
     }
-    // the whole workgroup leaves when the run has ended (the flag, read with
-    // the region, is the same for every lane)
-    if (HALT && __builtin_amdgcn_readfirstlane(halt)) return;
+    if (gate.ended(a)) return;
     __syncthreads();
+    if (gate.ends_now(a)) return;
     if (threadIdx.x < H) {  // one thread per class: exclusive scan over rows
         const int k = threadIdx.x;
         int run = 0;
@@ -667,29 +781,33 @@ __device__ __forceinline__ void tb_body_compact(const SweepArgs<typename Cell::T
 }
 
 // One region shape: rows x 64 cells, halo H, body KIND (TbKind).  HALT: the
-// launch may belong to a queued run that has already ended (SweepArgs::stop).
-template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC, bool HALT>
+// launch may belong to a queued run that has already ended (SweepArgs::stop);
+// PREV: it is the first launch of a queued interval that decides the
+// interval before it (SweepArgs::prev; never a check launch).
+template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC, bool HALT,
+          bool PREV>
 __device__ __forceinline__ void tb_dispatch(const SweepArgs<typename Cell::T> &a, const int t,
                                             const int steps, double *part_out) {
     if constexpr (KIND == kTbCompact)
-        tb_body_compact<Cell, RH, H, NT, CHECK, BC, HALT>(a, t, steps, part_out);
+        tb_body_compact<Cell, RH, H, NT, CHECK, BC, HALT, PREV>(a, t, steps, part_out);
     else if constexpr (KIND == kTbInPlace)
-        tb_body_inplace<Cell, RH, H, NT, CHECK, BC, HALT>(a, t, steps, part_out);
+        tb_body_inplace<Cell, RH, H, NT, CHECK, BC, HALT, PREV>(a, t, steps, part_out);
     else
-        tb_body<Cell, RH, H, NT, CHECK, BC, HALT>(a, t, steps, part_out);
+        tb_body<Cell, RH, H, NT, CHECK, BC, HALT, PREV>(a, t, steps, part_out);
 }
 
 // The tile list, the stop flag's lane copies (SweepArgs::stop) and the step
 // count come first, so that they arrive preloaded in scalar registers: the
 // tile's index and the flag are then requested at once, beside the remaining
 // arguments, instead of after them.
-template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC, bool PREV>
 __global__ __launch_bounds__(NT) void tb_kernel(const int32_t *__restrict__ tiles,
                                                 const int *__restrict__ stop, int steps,
                                                 SweepArgs<typename Cell::T> args) {
+    static_assert(!(CHECK && PREV), "a check launch does not decide the interval before it");
     SweepArgs<typename Cell::T> a = args;
     a.stop = stop;
-    tb_dispatch<Cell, RH, H, NT, KIND, CHECK, BC, true>(
+    tb_dispatch<Cell, RH, H, NT, KIND, CHECK, BC, true, PREV>(
         a, tiles[blockIdx.x], steps, CHECK ? a.partials + (size_t)blockIdx.x * 4 : nullptr);
 }
 
@@ -703,7 +821,8 @@ __global__ __launch_bounds__(NT) void tb_batch_kernel(
     const int l = lat[blockIdx.x];
     if (l < 0) return;
     const SweepArgs<typename Cell::T> a = args[l];
-    tb_dispatch<Cell, RH, H, NT, KIND, false, BC, false>(a, tiles[blockIdx.x], steps, nullptr);
+    tb_dispatch<Cell, RH, H, NT, KIND, false, BC, false, false>(a, tiles[blockIdx.x], steps,
+                                                                 nullptr);
 }
 
 // Dynamic LDS of one region shape.
@@ -737,11 +856,11 @@ inline hipError_t set_lds(const void *k, size_t lds, bool &done) {
     return e;
 }
 
-template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC>
+template <class Cell, int RH, int H, int NT, int KIND, bool CHECK, bool BC, bool PREV = false>
 hipError_t launch_tb_one(const SweepArgs<typename Cell::T> &a, const int32_t *tiles, int n_tiles,
                          int steps, hipStream_t s) {
     const size_t lds = tb_lds_bytes<typename Cell::T, RH, KIND>();
-    auto k = tb_kernel<Cell, RH, H, NT, KIND, CHECK, BC>;
+    auto k = tb_kernel<Cell, RH, H, NT, KIND, CHECK, BC, PREV>;
     static bool configured = false;  // one flag per kernel instantiation
     const hipError_t e = set_lds((const void *)k, lds, configured);
     if (e != hipSuccess) return e;
@@ -755,6 +874,14 @@ hipError_t launch_tb(const SweepArgs<typename Cell::T> &a, const int32_t *tiles,
     if (n_tiles <= 0 || steps <= 0) return hipSuccess;
     if (steps > H) return hipErrorInvalidValue;
     const bool bc = a.flags != 0;
+    if (a.prev) {
+        if (check || n_tiles > kDeferMaxPartials) return hipErrorInvalidValue;
+        if (bc)
+            return launch_tb_one<Cell, RH, H, NT, KIND, false, true, true>(a, tiles, n_tiles,
+                                                                           steps, s);
+        return launch_tb_one<Cell, RH, H, NT, KIND, false, false, true>(a, tiles, n_tiles, steps,
+                                                                        s);
+    }
     if (check && bc)
         return launch_tb_one<Cell, RH, H, NT, KIND, true, true>(a, tiles, n_tiles, steps, s);
     if (check)

@@ -764,6 +764,36 @@ def test_bitwise_deterministic():
     assert np.array_equal(out[0][2], out[1][2])
 
 
+@pytest.mark.parametrize("prec,tol", [(lbm.LBM_F64, 1e-7), (lbm.LBM_F32, 3e-6)])
+def test_deferred_finalize_matches_finalize_launches(prec, tol, monkeypatch):
+    """On a lattice of few tiles, the first launch of each queued interval
+    decides the interval before it.  The stopping step, the residual (the same
+    sums, bit for bit), the state and the unstable report are those of runs
+    that give every interval a finalize launch of its own (LBM_DEFER=0)."""
+    wl = I.CORRECTNESS_128x64
+    t = wl.types()
+    out = []
+    for defer in ("1", "0"):
+        monkeypatch.setenv("LBM_DEFER", defer)
+        a = lbm.Lattice(t, wl.tau, wl.u_peak, precision=prec)
+        rc, steps, r = a.run(200000, tol, 100)
+        s1 = a.state()
+        rc2, steps2, r2 = a.run(3456, 0.0, 100)  # several full batches, a short last interval
+        s2 = a.state()
+        rc3, steps3, r3 = a.run(2345, tol, 7)  # intervals shorter than one launch
+        s3 = a.state()
+        a.close()
+        u = lbm.Lattice(I.channel(64, 18), 0.5005, 0.3, precision=prec)  # blows up
+        rc4, steps4, _ = u.run(5000, 0.0, 50)
+        u.close()
+        out.append(((rc, steps, r, rc2, steps2, r2, rc3, steps3, r3, rc4, steps4), (s1, s2, s3)))
+        report(f"deferred finalize {defer} prec={prec}", steps=steps, r=r, unstable_at=steps4)
+    assert out[0][0] == out[1][0]
+    assert out[0][0][0] == lbm.LBM_OK and out[0][0][-2] == lbm.LBM_EUNSTABLE
+    for x, y in zip(out[0][1], out[1][1]):
+        assert np.array_equal(x, y)
+
+
 def test_run_timing_covers_every_fourth_interval():
     """Sweep timing inside a run (the benchmark's launch time) records the
     first of every four check intervals since it was enabled: over ten
