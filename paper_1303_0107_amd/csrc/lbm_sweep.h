@@ -218,20 +218,28 @@ struct RunGate {
     }
 
     // After the first barrier: true when the previous interval ends the run.
+    // Wave 0 alone forms the totals and the decision and hands the decision
+    // to the other waves through LDS (one more barrier, in this launch only).
     template <typename T>
     __device__ __forceinline__ bool ends_now(const SweepArgs<T> &a) {
         if (!HALT || !PREV) return false;
-        double v[4];
+        __shared__ int s_stop;
+        if (threadIdx.x < 64) {
+            double v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            double s = wave_sums()[0][k];
-            for (int w = 1; w < 4; ++w) s += wave_sums()[w][k];
-            v[k] = s;
+            for (int k = 0; k < 4; ++k) {
+                double s = wave_sums()[0][k];
+                for (int w = 1; w < 4; ++w) s += wave_sums()[w][k];
+                v[k] = s;
+            }
+            const int stop = interval_stop(v, a.tol);
+            if (threadIdx.x == 0) {
+                s_stop = stop;
+                if (blockIdx.x == 0) record_interval(a.ctl, a.prev_j, v, stop, a.stop_out, nullptr);
+            }
         }
-        const int stop = interval_stop(v, a.tol);
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            record_interval(a.ctl, a.prev_j, v, stop, a.stop_out, nullptr);
-        return stop != 0;
+        __syncthreads();
+        return s_stop != 0;
     }
 };
 
